@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput of the dense FP64 triangular solve with many right-hand sides.
+
+Workload: op(A) X = B with A lower-triangular n x n, no transpose, non-unit
+diagonal, alpha = 1, n = nrhs = 8192, column-major, FP64; A's strict lower
+part i.i.d. U(-1, 1) with diagonal 1 + sum |row|, B i.i.d. N(0, 1), seeded.
+One step = restore B from a pristine device copy, then one full solve through
+the C-ABI (redsea_trsm).  Flops are counted as n^2 * nrhs per solve.
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (the MFMA product update, timed live with HIP events through the
+library's trace API) and the CPU oracle timed on a bounded sample of the
+same workload (a subset of right-hand-side columns) on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(L, B, n, budget_s, threads):
+    """Time the plain CPU oracle on a subset of columns of the same system."""
+    import numpy as np
+    import oracle
+    # pilot: one column per thread
+    cols = threads
+    t0 = time.perf_counter()
+    oracle.trsm_plain(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, :cols]), nthreads=threads)
+    pilot = time.perf_counter() - t0
+    reps = max(1, int(budget_s / max(pilot, 1e-3)))
+    cols = min(B.shape[1], threads * reps)
+    t0 = time.perf_counter()
+    oracle.trsm_plain(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, :cols]), nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(float(n) * n * cols / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "plain FP64 substitution of the first %d of %d right-hand-side columns of "
+                      "the same n=%d system (%.1f s)" % (cols, B.shape[1], n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--nrhs", type=int, default=8192)
+    ap.add_argument("--variant", default="recursive")
+    ap.add_argument("--nb", type=int, default=64)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the solve shards by right-hand-side columns "
+              "across GPUs, but this build runs and reports a single MI355X (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2305_19917_amd as rs
+    import synth
+
+    if not os.path.exists(rs.LIB_PATH):
+        from paper_2305_19917_amd import build as libbuild
+        libbuild.build()
+    rs.lib()
+    n, nrhs = args.n, args.nrhs
+    log("generating n=%d nrhs=%d" % (n, nrhs))
+    L = synth.dominant_lower(n, (1, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+    dev = torch.device("cuda:0")
+    dA = rs.fortran_tensor(L, dev)
+    dB0 = rs.fortran_tensor(B, dev)
+    dB = rs.fortran_tensor(np.zeros((n, nrhs)), dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        dB.copy_(dB0)
+        rs.trsm(dA, dB, variant=args.variant, nb=args.nb, stream=stream)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log("timed %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    flops = float(n) * n * nrhs
+    value = flops / (ms_per_step * 1e-3) / 1e12
+
+    # solve-only time per step (events around the solve, restore excluded)
+    solve_ms = []
+    for _ in range(args.steps):
+        dB.copy_(dB0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rs.trsm(dA, dB, variant=args.variant, nb=args.nb, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        solve_ms.append(e0.elapsed_time(e1))
+    solve_ms.sort()
+    solve_med = solve_ms[len(solve_ms) // 2]
+
+    # dominant kernel: the product update, timed per launch with HIP events on
+    # the library's stream over the same number of steps
+    log("traced %d steps" % args.steps)
+    rs.trace_begin()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tr = rs.trace_end()
+    g_launch, g_ms, g_fl = tr["gemm"]
+    achieved = g_fl / (g_ms * 1e-3) / 1e12 if g_ms > 0 else 0.0
+    shares = {k: round(v[1] / args.steps, 4) for k, v in tr.items()}
+
+    # sampled parity of the final result against the CPU oracle
+    import oracle
+    cols = [0, nrhs // 2, nrhs - 1]
+    Xs = dB[:, cols].cpu().numpy()
+    eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, cols]), Xs)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+        log("cpu baseline, %d threads" % threads)
+        cpu = cpu_baseline(L, B, n, args.cpu_seconds, threads)
+
+    out = {
+        "metric": "TRSM TFLOP/s (n^2*nrhs): FP64",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 TRSM left/lower/no-transpose/non-unit, n=%d, nrhs=%d, "
+                               "alpha=1, column-major, %s schedule, leaf nb=%d"
+                               % (n, nrhs, args.variant, args.nb),
+                   "n": n, "nrhs": nrhs, "variant": args.variant, "nb": args.nb},
+        "solve_ms_median": round(solve_med, 4),
+        "solve_tflops": round(flops / (solve_med * 1e-3) / 1e12, 3),
+        "frac_of_fp64_peak": round(value / FP64_MFMA_PEAK, 4),
+        "kernel_ms_per_step": shares,
+        "eta_sampled": eta,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK, 4),
+                     "traffic": None, "kernel": "gemm_kernel<double> (product update)",
+                     "launches_per_step": g_launch // max(1, args.steps)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * redsea.h -- C interface of libredsea, a dense triangular solver with many
+ * right-hand sides for AMD MI355X (gfx950).
+ *
+ * The computation is the one the ReDSEa paper (arXiv 2305.19917) maps and
+ * schedules: the triangular system L x = b of Sec. IV, extended to many
+ * right-hand sides that share L, solved by splitting L into a top-left
+ * triangle, a bottom-left rectangle and a bottom-right triangle (solve, then
+ * update the lower right-hand sides with a matrix product, then solve),
+ * arranged in the recursive, iterative or blocked models of computation of
+ * Sec. V-A, V-B and V-C.  On top of that the library follows BLAS xTRSM
+ * semantics:
+ *
+ *     side = REDSEA_LEFT :  op(A) X = alpha B      (A is m x m)
+ *     side = REDSEA_RIGHT:  X op(A) = alpha B      (A is n x n)
+ *
+ * with B an m x n matrix that X overwrites, op(A) = A or A^T, A lower or
+ * upper triangular (only that triangle is read), and a unit diagonal that is
+ * never read when diag = REDSEA_UNIT.
+ *
+ * Conventions shared by every entry point:
+ *   - All matrices are column-major.  Matrix pointers are DEVICE pointers
+ *     (memory from hipMalloc or a PyTorch CUDA/HIP tensor) unless a comment
+ *     says HOST.  The caller owns every buffer it passes; the library never
+ *     frees or retains them beyond the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are asynchronous on that stream unless stated otherwise.
+ *   - Return value (LAPACK info style):
+ *        0        success;
+ *       -i        argument number i (1-based) is invalid: a bad enum value,
+ *                 m or n < 0, lda < max(1, order of A), ldb < max(1, m), or
+ *                 a NULL pointer where data must be read or written;
+ *       >0        runtime failure, see redsea_status_string():
+ *                 REDSEA_ERR_HIP (a HIP call failed), REDSEA_ERR_ALLOC
+ *                 (device memory could not be obtained), REDSEA_ERR_NOCONV
+ *                 (iterative refinement did not converge and the FP64
+ *                 fallback is disabled), REDSEA_ERR_NONFINITE (non-finite
+ *                 value in a mixed-precision result),
+ *                 REDSEA_ERR_UNSUPPORTED (a valid combination this build
+ *                 does not implement).
+ *   - Quick return: m == 0 or n == 0 succeeds without touching memory.
+ *     alpha == 0 sets B to zero without reading A.
+ *   - As in BLAS there is no singularity check: a zero on a non-unit
+ *     diagonal propagates Inf/NaN into X.
+ */
+#ifndef REDSEA_H
+#define REDSEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { REDSEA_LEFT = 0, REDSEA_RIGHT = 1 } redsea_side;
+typedef enum { REDSEA_LOWER = 0, REDSEA_UPPER = 1 } redsea_uplo;
+/* For real data the conjugate transpose equals the transpose. */
+typedef enum { REDSEA_NOTRANS = 0, REDSEA_TRANS = 1, REDSEA_CONJTRANS = 2 } redsea_trans;
+typedef enum { REDSEA_NONUNIT = 0, REDSEA_UNIT = 1 } redsea_diag;
+typedef enum { REDSEA_F64 = 0, REDSEA_F32 = 1 } redsea_dtype;
+
+/* Model of computation (paper Sec. V). */
+typedef enum {
+    REDSEA_VARIANT_AUTO = 0,
+    REDSEA_VARIANT_RECURSIVE = 1, /* Sec. V-A: halve into TS, GEMM, TS down to the leaf size */
+    REDSEA_VARIANT_ITERATIVE = 2, /* Sec. V-B: fixed leaf size, one GEMM panel after each leaf */
+    REDSEA_VARIANT_BLOCKED = 3    /* Sec. V-C: r-1 rounds of equal leaf-size GEMM blocks */
+} redsea_variant;
+
+typedef enum {
+    REDSEA_PREC_AUTO = 0,
+    REDSEA_PREC_NATIVE = 1,   /* arithmetic in the data type            */
+    REDSEA_PREC_FP32_IR = 2,  /* FP32 solves + FP64 refinement (F64 only) */
+    REDSEA_PREC_BF16_IR = 3   /* BF16 products + FP64 refinement (F64 only) */
+} redsea_precision;
+
+/* Solver options; a NULL pointer means every field AUTO.  nb is the leaf
+ * (diagonal block) order; 0 = AUTO, otherwise one of 16, 32, 64, 128, 256,
+ * 512. */
+typedef struct {
+    int variant;   /* redsea_variant   */
+    int nb;        /* leaf size or 0   */
+    int precision; /* redsea_precision */
+} redsea_opts;
+
+enum {
+    REDSEA_OK = 0,
+    REDSEA_ERR_HIP = 1,
+    REDSEA_ERR_ALLOC = 2,
+    REDSEA_ERR_NOCONV = 3,
+    REDSEA_ERR_NONFINITE = 4,
+    REDSEA_ERR_UNSUPPORTED = 5
+};
+
+/*
+ * Solve op(A) X = alpha B (left) or X op(A) = alpha B (right) in place.
+ *
+ * Follows the three-stage split of Sec. IV applied recursively, iteratively
+ * or in blocked rounds (Sec. V) as selected by opts.  dtype gives the element
+ * type of A and B (double or float).  Argument numbers for the -i return:
+ * dtype 1, side 2, uplo 3, trans 4, diag 5, m 6, n 7, alpha 8, A 9, lda 10,
+ * B 11, ldb 12, opts 13, stream 14.  Temporary device memory (at most
+ * order(A) * nb elements plus a few KB) is taken from a per-device cache that
+ * the library grows on demand and keeps until the process ends.
+ */
+int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                double alpha, const void* A, int64_t lda, void* B, int64_t ldb,
+                const redsea_opts* opts, void* stream);
+
+/*
+ * Variable-size batch of independent solves sharing flags and alpha
+ * (spec batching pattern; each system is the solve of Sec. IV).
+ * m, n, lda, ldb: HOST arrays of `count` entries.  A, B: HOST arrays of
+ * `count` DEVICE pointers.  info: DEVICE int array of `count` entries that
+ * receives 0 or a positive per-system code (REDSEA_ERR_NONFINITE when the
+ * system's result holds a non-finite value).  The return value is 0, the -i
+ * code of the first invalid argument (for per-system arrays, i is the
+ * argument position), or a runtime failure code.  Argument numbers: dtype 1,
+ * side 2, uplo 3, trans 4, diag 5, count 6, m 7, n 8, alpha 9, A 10, lda 11,
+ * B 12, ldb 13, info 14, opts 15, stream 16.
+ */
+int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int64_t count,
+                        const int64_t* m, const int64_t* n, double alpha,
+                        const void* const* A, const int64_t* lda, void* const* B,
+                        const int64_t* ldb, int* info, const redsea_opts* opts, void* stream);
+
+/* Statistics of one mixed-precision solve (host struct). */
+typedef struct {
+    int iterations; /* refinement corrections applied            */
+    double eta;     /* last normwise backward error estimate      */
+    int fell_back;  /* 1 if the FP64 solve produced the result     */
+} redsea_mixed_stats;
+
+/*
+ * FP64 solve computed with low-precision inner solves and FP64 iterative
+ * refinement (spec precision pattern): X0 from an FP32 (inner = 1) or
+ * BF16-product (inner = 2) solve, then repeated R = alpha B - op(A) X in FP64,
+ * a low-precision correction solve and X += D in FP64, until the normwise
+ * backward error is at most tol (tol <= 0 means 1e-12) or max_iter
+ * (<= 0: 5 for FP32, 10 for BF16) is reached; on stagnation or no
+ * convergence it falls back to the FP64 solve.  inner = 0 picks
+ * automatically.  work/work_bytes: optional DEVICE workspace of at least
+ * redsea_trsm_mixed_workspace_bytes(...) bytes; NULL uses the library's
+ * cache.  stats: optional HOST struct.  This call synchronizes the stream
+ * once per refinement step to read the convergence test.  Argument numbers:
+ * side 1, uplo 2, trans 3, diag 4, m 5, n 6, alpha 7, A 8, lda 9, B 10,
+ * ldb 11, inner 12, tol 13, max_iter 14, work 15, work_bytes 16, stats 17,
+ * stream 18.
+ */
+int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                      double alpha, const double* A, int64_t lda, double* B, int64_t ldb,
+                      int inner, double tol, int max_iter, void* work, size_t work_bytes,
+                      redsea_mixed_stats* stats, void* stream);
+
+/* Bytes of device workspace redsea_trsm_mixed needs for this shape. */
+size_t redsea_trsm_mixed_workspace_bytes(int side, int64_t m, int64_t n, int inner);
+
+/* Static, human-readable text for a return code. */
+const char* redsea_status_string(int code);
+
+/*
+ * Schedule inspection (HOST only, no device work): writes the task list the
+ * planner builds for a lower-triangular order-m solve with leaf size nb and
+ * the given variant, in canonical (forward-substitution) coordinates.
+ * Each task is 6 int64 values {kind, row0, rows, col0, cols, round}:
+ *   kind 0 = leaf solve of rows [row0, row0+rows);
+ *   kind 1 = product update B[row0:row0+rows] -= T[row0:.., col0:col0+cols] X[col0:..];
+ *   round  = launch group (tasks with equal round run in one launch).
+ * Returns the number of tasks (also when it exceeds max_tasks, in which case
+ * only max_tasks are written), or a negative -i for an invalid argument.
+ * Follows the recursive split of Sec. V-A, the iterative panels of Sec. V-B
+ * and the blocked rounds of Sec. V-C.
+ */
+int64_t redsea_schedule(int variant, int64_t m, int nb, int64_t* tasks, int64_t max_tasks);
+
+/*
+ * Kernel timing trace (HOST calls).  Between redsea_trace_begin() and
+ * redsea_trace_end() every kernel the solver launches is bracketed by HIP
+ * events on its stream.  redsea_trace_end() waits for those events and
+ * writes, for each kernel class k < nkinds (REDSEA_KERNEL_*), the number of
+ * launches, their summed duration in milliseconds and their summed
+ * algorithmic flops (product: 2*M*N*K; leaf: rows^2 * right-hand sides).
+ * The three output arrays are HOST arrays of nkinds entries owned by the
+ * caller.  Returns 0, -4 for bad arrays, or REDSEA_ERR_HIP.  Tracing adds a
+ * pair of event records per launch; it is meant for measurement, not for
+ * production calls.
+ */
+enum {
+    REDSEA_KERNEL_PACK = 0,       /* diagonal-block packing            */
+    REDSEA_KERNEL_LEAF = 1,       /* leaf solve (Sec. V white triangles) */
+    REDSEA_KERNEL_GEMM = 2,       /* one product update (grey rectangle) */
+    REDSEA_KERNEL_GEMM_GROUP = 3, /* one blocked round of products       */
+    REDSEA_KERNEL_CLASSES = 4
+};
+void redsea_trace_begin(void);
+int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds);
+
+/* Library version as "major.minor.patch". */
+const char* redsea_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REDSEA_H */

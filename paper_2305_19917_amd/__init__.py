@@ -1,0 +1,13 @@
+"""redsea: dense triangular solve with many right-hand sides on MI355X.
+
+Thin Python face of the C library libredsea.so (include/redsea.h).  The
+functions here only marshal arguments; the solves run in the library's HIP
+kernels for gfx950.
+"""
+from ._binding import (EXPORTS, KERNEL_CLASSES, LIB_PATH, trace_begin, trace_end, MixedStats, Opts, RedseaError, fortran_tensor, lib,
+                       mixed_workspace_bytes, schedule, status_string, trsm, trsm_batched,
+                       trsm_mixed, version)
+
+__all__ = ["EXPORTS", "KERNEL_CLASSES", "LIB_PATH", "trace_begin", "trace_end", "MixedStats", "Opts", "RedseaError", "fortran_tensor", "lib",
+           "mixed_workspace_bytes", "schedule", "status_string", "trsm", "trsm_batched",
+           "trsm_mixed", "version"]

@@ -1,0 +1,217 @@
+"""ctypes binding of libredsea.so: argument marshalling only.
+
+Every step of a solve runs in the library's HIP kernels; this module turns
+PyTorch tensors into pointers, leading dimensions and a stream handle.  It
+never computes a result itself and has no CPU fallback: if the library is
+missing, importing a function raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libredsea.so")
+
+# Symbols the public header declares.
+EXPORTS = (
+    "redsea_trsm",
+    "redsea_trsm_batched",
+    "redsea_trsm_mixed",
+    "redsea_trsm_mixed_workspace_bytes",
+    "redsea_status_string",
+    "redsea_schedule",
+    "redsea_version",
+    "redsea_trace_begin",
+    "redsea_trace_end",
+)
+KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group")
+
+SIDE = {"L": 0, "R": 1, 0: 0, 1: 1}
+UPLO = {"L": 0, "U": 1, 0: 0, 1: 1}
+TRANS = {"N": 0, "T": 1, "C": 2, 0: 0, 1: 1, 2: 2}
+DIAG = {"N": 0, "U": 1, 0: 0, 1: 1}
+VARIANT = {"auto": 0, "recursive": 1, "iterative": 2, "blocked": 3, 0: 0, 1: 1, 2: 2, 3: 3}
+PRECISION = {"auto": 0, "native": 1, "fp32_ir": 2, "bf16_ir": 3, 0: 0, 1: 1, 2: 2, 3: 3}
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+class RedseaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("redsea error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("nb", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class MixedStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("eta", ctypes.c_double), ("fell_back", ctypes.c_int)]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libredsea.so (built by paper_2305_19917_amd.build); raises if absent."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libredsea.so is not built: run paper_2305_19917_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, dbl, ptr, cint, sz = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    L.redsea_trsm.restype = cint
+    L.redsea_trsm.argtypes = [cint, cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64,
+                              ctypes.POINTER(Opts), ptr]
+    L.redsea_trsm_batched.restype = cint
+    L.redsea_trsm_batched.argtypes = [cint, cint, cint, cint, cint, i64, ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), dbl, ctypes.POINTER(ptr),
+                                      ctypes.POINTER(i64), ctypes.POINTER(ptr),
+                                      ctypes.POINTER(i64), ptr, ctypes.POINTER(Opts), ptr]
+    L.redsea_trsm_mixed.restype = cint
+    L.redsea_trsm_mixed.argtypes = [cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64,
+                                    cint, dbl, cint, ptr, sz, ctypes.POINTER(MixedStats), ptr]
+    L.redsea_trsm_mixed_workspace_bytes.restype = sz
+    L.redsea_trsm_mixed_workspace_bytes.argtypes = [cint, i64, i64, cint]
+    L.redsea_status_string.restype = ctypes.c_char_p
+    L.redsea_status_string.argtypes = [cint]
+    L.redsea_schedule.restype = i64
+    L.redsea_schedule.argtypes = [cint, i64, cint, ptr, i64]
+    L.redsea_version.restype = ctypes.c_char_p
+    L.redsea_version.argtypes = []
+    L.redsea_trace_begin.restype = None
+    L.redsea_trace_begin.argtypes = []
+    L.redsea_trace_end.restype = cint
+    L.redsea_trace_end.argtypes = [ptr, ptr, ptr, cint]
+    _LIB = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return lib().redsea_status_string(code).decode()
+
+
+def _check(code: int):
+    if code != 0:
+        raise RedseaError(code, status_string(code))
+
+
+def _ld(t) -> int:
+    """Leading dimension of a column-major 2-D tensor view (stride(0) == 1)."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.shape[0] > 1 and t.shape[1] > 1 and t.stride(0) != 1:
+        raise ValueError("tensor must be column-major (stride(0) == 1); use fortran_tensor()")
+    if t.shape[1] <= 1:
+        return max(1, t.shape[0])
+    return max(1, t.stride(1))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError("only float64 and float32 tensors are supported")
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def fortran_tensor(arr, device="cuda"):
+    """Copy a 2-D numpy array to `device` as a column-major tensor (ld = rows)."""
+    import numpy as np
+    import torch
+    a = np.asarray(arr)
+    t = torch.from_numpy(np.ascontiguousarray(a.T)).to(device)
+    return t.t()
+
+
+def trsm(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
+         variant="auto", nb: int = 0, precision="auto", stream=None):
+    """In place: B := alpha op(A)^{-1} B (side L) or alpha B op(A)^{-1} (side R).
+
+    A and B are column-major device tensors of the same dtype.  Returns B."""
+    m, n = B.shape
+    opts = Opts(VARIANT[variant], int(nb), PRECISION[precision])
+    rc = lib().redsea_trsm(_dtype_code(B), SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag],
+                           m, n, float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
+                           ctypes.byref(opts), _stream(stream))
+    _check(rc)
+    return B
+
+
+def trsm_batched(As: Sequence, Bs: Sequence, info, side="L", uplo="L", trans="N", diag="N",
+                 alpha: float = 1.0, variant="auto", nb: int = 0, stream=None):
+    """Batch of independent in-place solves; info is an int32 device tensor."""
+    count = len(Bs)
+    i64 = ctypes.c_int64
+    ms = (i64 * count)(*[b.shape[0] for b in Bs])
+    ns = (i64 * count)(*[b.shape[1] for b in Bs])
+    ldas = (i64 * count)(*[_ld(a) for a in As])
+    ldbs = (i64 * count)(*[_ld(b) for b in Bs])
+    aps = (ctypes.c_void_p * count)(*[a.data_ptr() for a in As])
+    bps = (ctypes.c_void_p * count)(*[b.data_ptr() for b in Bs])
+    opts = Opts(VARIANT[variant], int(nb), 0)
+    dt = _dtype_code(Bs[0]) if count else 0
+    rc = lib().redsea_trsm_batched(dt, SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag], count,
+                                   ms, ns, float(alpha), aps, ldas, bps, ldbs, info.data_ptr(),
+                                   ctypes.byref(opts), _stream(stream))
+    _check(rc)
+
+
+def trsm_mixed(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0, inner: int = 0,
+               tol: float = 0.0, max_iter: int = 0, work=None, stream=None) -> MixedStats:
+    """FP64 solve by low-precision solves and FP64 iterative refinement."""
+    m, n = B.shape
+    st = MixedStats()
+    wp = work.data_ptr() if work is not None else None
+    wb = work.numel() * work.element_size() if work is not None else 0
+    rc = lib().redsea_trsm_mixed(SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag], m, n,
+                                 float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
+                                 int(inner), float(tol), int(max_iter), wp, wb,
+                                 ctypes.byref(st), _stream(stream))
+    _check(rc)
+    return st
+
+
+def mixed_workspace_bytes(side, m: int, n: int, inner: int) -> int:
+    return int(lib().redsea_trsm_mixed_workspace_bytes(SIDE[side], m, n, inner))
+
+
+def schedule(variant, m: int, nb: int):
+    """Task list of the planner as a list of (kind, row0, rows, col0, cols, round)."""
+    L = lib()
+    cnt = L.redsea_schedule(VARIANT[variant], m, nb, None, 0)
+    if cnt < 0:
+        raise RedseaError(int(cnt), "invalid argument")
+    buf = (ctypes.c_int64 * (6 * max(1, cnt)))()
+    L.redsea_schedule(VARIANT[variant], m, nb, ctypes.cast(buf, ctypes.c_void_p), cnt)
+    return [tuple(buf[6 * i:6 * i + 6]) for i in range(cnt)]
+
+
+def version() -> str:
+    return lib().redsea_version().decode()
+
+
+def trace_begin():
+    """Start timing every kernel launch of the solver with HIP events."""
+    lib().redsea_trace_begin()
+
+
+def trace_end():
+    """Stop tracing; returns {class: (launches, total_ms, total_flops)}."""
+    n = len(KERNEL_CLASSES)
+    la = (ctypes.c_int64 * n)()
+    ms = (ctypes.c_double * n)()
+    fl = (ctypes.c_double * n)()
+    _check(lib().redsea_trace_end(ctypes.cast(la, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p),
+                                  ctypes.cast(fl, ctypes.c_void_p), n))
+    return {k: (int(la[i]), float(ms[i]), float(fl[i])) for i, k in enumerate(KERNEL_CLASSES)}

@@ -1,0 +1,479 @@
+// C interface of libredsea: argument checks, canonicalisation of the BLAS
+// flags onto one forward-substitution family, schedule construction and
+// execution on a HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/redsea.h"
+#include "exec.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace redsea {
+
+// ------------------------------------------------------------------ workspace
+namespace {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, int>, DevBuf> g_ws;  // (device, slot) -> buffer
+
+}  // namespace
+
+int workspace(int slot, size_t bytes, void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return REDSEA_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    DevBuf& b = g_ws[{dev, slot}];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            if (hipDeviceSynchronize() != hipSuccess) return REDSEA_ERR_HIP;
+            if (hipFree(b.ptr) != hipSuccess) return REDSEA_ERR_HIP;
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 4;
+        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return REDSEA_ERR_ALLOC;
+        }
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return REDSEA_OK;
+}
+
+// ------------------------------------------------------------------ canonical form
+
+Canon canonicalize(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                   const void* A, int64_t lda, void* B, int64_t ldb) {
+    Canon c;
+    c.dtype = dtype;
+    c.unit = diag == REDSEA_UNIT;
+    // Right side: X op(A) = alpha B  <=>  op(A)^T X^T = alpha B^T, a left
+    // solve with the transpose flag flipped on the transposed right-hand side.
+    const bool right = side == REDSEA_RIGHT;
+    c.op_trans = right ? (trans == REDSEA_NOTRANS) : (trans != REDSEA_NOTRANS);
+    c.rhs_trans = right;
+    c.k = right ? n : m;
+    c.nrhs = right ? m : n;
+    // M = op_eff(A) is lower iff (A lower) xor transposed.
+    const bool m_lower = (uplo == REDSEA_LOWER) != c.op_trans;
+    c.reverse = !m_lower;
+    c.A = A;
+    c.lda = lda;
+    c.B = B;
+    c.ldb = ldb;
+    const int64_t k = c.k;
+    // Canonical T(i, j) = M(i, j), or M(k-1-i, k-1-j) when reversed.
+    c.tri.base = A;
+    if (!c.reverse) {
+        c.tri.off = 0;
+        c.tri.tr = c.op_trans ? lda : 1;
+        c.tri.tc = c.op_trans ? 1 : lda;
+    } else {
+        c.tri.off = (k - 1) * (1 + lda);
+        c.tri.tr = c.op_trans ? -lda : -1;
+        c.tri.tc = c.op_trans ? -1 : -lda;
+    }
+    // Canonical right-hand sides: column j of the left problem.
+    c.rhs.base = B;
+    const int64_t s_row = right ? ldb : 1, s_col = right ? 1 : ldb;
+    if (!c.reverse) {
+        c.rhs.off = 0;
+        c.rhs.br = s_row;
+    } else {
+        c.rhs.off = (k - 1) * s_row;
+        c.rhs.br = -s_row;
+    }
+    c.rhs.bc = s_col;
+    return c;
+}
+
+// Product task in storage coordinates: canonical rows [r0, r0+R) of C and
+// canonical columns [c0, c0+K) of T become storage rows of M = op_eff(A).
+GemmArgs gemm_args(const Canon& c, int64_t r0, int64_t R, int64_t c0, int64_t K) {
+    const int64_t k = c.k;
+    int64_t R0 = r0, K0 = c0;
+    if (c.reverse) {
+        R0 = k - r0 - R;
+        K0 = k - c0 - K;
+    }
+    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
+    GemmArgs g;
+    g.M = R;
+    g.N = c.nrhs;
+    g.K = K;
+    const char* a = (const char*)c.A;
+    // M(i, j) = A[i + j*lda] (not transposed) or A[j + i*lda] (transposed)
+    g.a = c.op_trans ? a + es * (K0 + R0 * c.lda) : a + es * (R0 + K0 * c.lda);
+    g.lda = c.lda;
+    char* b = (char*)c.B;
+    if (!c.rhs_trans) {
+        g.x = b + es * K0;
+        g.c = b + es * R0;
+    } else {
+        g.x = b + es * (K0 * c.ldb);
+        g.c = b + es * (R0 * c.ldb);
+    }
+    g.ldx = c.ldb;
+    g.ldc = c.ldb;
+    return g;
+}
+
+// ------------------------------------------------------------------ plans
+
+namespace {
+
+std::mutex g_plan_mu;
+std::map<std::tuple<int, int64_t, int64_t>, std::vector<Task>> g_plans;
+
+// Leaves larger than the leaf kernel's register block are themselves solved
+// by the recursive split (Sec. V-A) down to that block.
+std::vector<Task> expand_leaves(const std::vector<Task>& in, int64_t kleaf) {
+    std::vector<Task> out;
+    int64_t round = 0, last = -1;
+    for (const Task& t : in) {
+        if (t.round != last) {
+            last = t.round;
+            ++round;
+        }
+        if (t.kind == TASK_LEAF && t.rows > kleaf) {
+            std::vector<Task> sub = build_schedule(VAR_RECURSIVE, t.rows, kleaf);
+            for (Task s : sub) {
+                s.row0 += t.row0;
+                s.col0 += t.row0;
+                s.round = round++;
+                out.push_back(s);
+            }
+        } else {
+            Task s = t;
+            s.round = round;
+            out.push_back(s);
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+const std::vector<Task>& plan_for(int variant, int64_t k, int64_t nb, int64_t kleaf) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto key = std::make_tuple(variant, k, nb * 1024 + kleaf);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) return it->second;
+    std::vector<Task> t = expand_leaves(build_schedule(variant, k, nb), kleaf);
+    return g_plans.emplace(key, std::move(t)).first->second;
+}
+
+// ------------------------------------------------------------------ tracing
+// When enabled, every kernel launch of the executor is bracketed by a pair of
+// HIP events on its stream; redsea_trace_end() waits for them and returns the
+// summed durations and algorithmic flops per kernel class.
+
+namespace {
+
+struct TraceRec {
+    int kind;
+    double flops;
+    hipEvent_t e0, e1;
+};
+
+std::mutex g_tr_mu;
+bool g_tr_on = false;
+std::vector<TraceRec> g_tr;
+
+}  // namespace
+
+bool trace_on() { return g_tr_on; }
+
+void trace_push(int kind, double flops, hipEvent_t e0, hipEvent_t e1) {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    g_tr.push_back({kind, flops, e0, e1});
+}
+
+// Runs `launch` and, when tracing, records events around it.
+template <typename F>
+hipError_t traced(int kind, double flops, hipStream_t s, F&& launch) {
+    if (!g_tr_on) return launch();
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hipErrorOutOfMemory;
+    }
+    (void)hipEventRecord(e0, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(e1, s);
+    trace_push(kind, flops, e0, e1);
+    return e;
+}
+
+// ------------------------------------------------------------------ execution
+
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
+    const int64_t kleaf = std::min<int64_t>(nb, 64);
+    const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
+    const int64_t nblk = (c.k + kleaf - 1) / kleaf;
+    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
+    void* packed = nullptr;
+    int rc = workspace(0, (size_t)nblk * kleaf * kleaf * es, &packed);
+    if (rc) return rc;
+    if (traced(REDSEA_KERNEL_PACK, 0.0, s, [&] {
+            return launch_pack_diag(c.dtype, c.tri, c.k, (int)kleaf, 0, nblk, c.unit, packed, s);
+        }) != hipSuccess)
+        return REDSEA_ERR_HIP;
+    size_t i = 0;
+    while (i < tasks.size()) {
+        const Task& t = tasks[i];
+        if (t.kind == TASK_LEAF) {
+            const char* pb = (const char*)packed + (size_t)(t.row0 / kleaf) * kleaf * kleaf * es;
+            const double fl = (double)t.rows * t.rows * c.nrhs;
+            if (traced(REDSEA_KERNEL_LEAF, fl, s, [&] {
+                    return launch_leaf(c.dtype, (int)kleaf, pb, t.rows, c.rhs, t.row0, c.nrhs,
+                                       c.unit, s);
+                }) != hipSuccess)
+                return REDSEA_ERR_HIP;
+            ++i;
+            continue;
+        }
+        // gather the products of this round
+        size_t j = i;
+        while (j < tasks.size() && tasks[j].kind == TASK_GEMM && tasks[j].round == t.round) ++j;
+        if (j - i == 1) {
+            GemmArgs g = gemm_args(c, t.row0, t.rows, t.col0, t.cols);
+            const double fl = 2.0 * g.M * g.N * g.K;
+            if (traced(REDSEA_KERNEL_GEMM, fl, s,
+                       [&] { return launch_gemm(c.dtype, c.op_trans, c.rhs_trans, g, s); }) !=
+                hipSuccess)
+                return REDSEA_ERR_HIP;
+        } else {
+            GemmGroup grp;
+            grp.count = 0;
+            for (size_t q = i; q < j; ++q) {
+                grp.g[grp.count++] = gemm_args(c, tasks[q].row0, tasks[q].rows, tasks[q].col0,
+                                               tasks[q].cols);
+                if (grp.count == kMaxGroup || q + 1 == j) {
+                    double fl = 0.0;
+                    for (int u = 0; u < grp.count; ++u)
+                        fl += 2.0 * grp.g[u].M * grp.g[u].N * grp.g[u].K;
+                    if (traced(REDSEA_KERNEL_GEMM_GROUP, fl, s, [&] {
+                            return launch_gemm_group(c.dtype, c.op_trans, c.rhs_trans, grp, s);
+                        }) != hipSuccess)
+                        return REDSEA_ERR_HIP;
+                    grp.count = 0;
+                }
+            }
+        }
+        i = j;
+    }
+    return REDSEA_OK;
+}
+
+int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (side != REDSEA_LEFT && side != REDSEA_RIGHT) return -2;
+    if (uplo != REDSEA_LOWER && uplo != REDSEA_UPPER) return -3;
+    if (trans != REDSEA_NOTRANS && trans != REDSEA_TRANS && trans != REDSEA_CONJTRANS) return -4;
+    if (diag != REDSEA_NONUNIT && diag != REDSEA_UNIT) return -5;
+    if (m < 0) return -6;
+    if (n < 0) return -7;
+    const int64_t ka = side == REDSEA_LEFT ? m : n;
+    if (lda < std::max<int64_t>(1, ka)) return -10;
+    if (ldb < std::max<int64_t>(1, m)) return -12;
+    if (m > 0 && n > 0) {
+        if (need_a && A == nullptr) return -9;
+        if (B == nullptr) return -11;
+    }
+    return 0;
+}
+
+int pick_nb(int requested, int64_t k) {
+    if (requested > 0) return requested;
+    (void)k;
+    return 64;
+}
+
+}  // namespace redsea
+
+using namespace redsea;
+
+extern "C" {
+
+const char* redsea_version(void) { return "0.1.0"; }
+
+const char* redsea_status_string(int code) {
+    if (code < 0) return "invalid argument";
+    switch (code) {
+        case REDSEA_OK: return "success";
+        case REDSEA_ERR_HIP: return "HIP runtime error";
+        case REDSEA_ERR_ALLOC: return "device memory allocation failed";
+        case REDSEA_ERR_NOCONV: return "iterative refinement did not converge";
+        case REDSEA_ERR_NONFINITE: return "non-finite value in result";
+        case REDSEA_ERR_UNSUPPORTED: return "unsupported combination";
+        default: return "unknown status";
+    }
+}
+
+int64_t redsea_schedule(int variant, int64_t m, int nb, int64_t* tasks, int64_t max_tasks) {
+    if (variant < 0 || variant > 3) return -1;
+    if (m < 0) return -2;
+    if (nb <= 0) return -3;
+    if (max_tasks > 0 && tasks == nullptr) return -4;
+    std::vector<Task> t = build_schedule(variant == 0 ? VAR_RECURSIVE : variant, m, nb);
+    for (int64_t i = 0; i < (int64_t)t.size() && i < max_tasks; ++i) {
+        tasks[6 * i + 0] = t[i].kind;
+        tasks[6 * i + 1] = t[i].row0;
+        tasks[6 * i + 2] = t[i].rows;
+        tasks[6 * i + 3] = t[i].col0;
+        tasks[6 * i + 4] = t[i].cols;
+        tasks[6 * i + 5] = t[i].round;
+    }
+    return (int64_t)t.size();
+}
+
+int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                double alpha, const void* A, int64_t lda, void* B, int64_t ldb,
+                const redsea_opts* opts, void* stream) {
+    int rc = check_args(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb, alpha != 0.0);
+    if (rc) return rc;
+    int variant = opts ? opts->variant : 0;
+    int nb = opts ? opts->nb : 0;
+    int precision = opts ? opts->precision : 0;
+    if (variant < 0 || variant > 3) return -13;
+    if (!(nb == 0 || nb == 16 || nb == 32 || nb == 64 || nb == 128 || nb == 256 || nb == 512))
+        return -13;
+    if (precision < 0 || precision > 3) return -13;
+    if (m == 0 || n == 0) return REDSEA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0 || alpha != 1.0) {
+        if (launch_scale(dtype, B, m, n, ldb, alpha, s) != hipSuccess) return REDSEA_ERR_HIP;
+        if (alpha == 0.0) return REDSEA_OK;
+    }
+    if (precision == REDSEA_PREC_FP32_IR || precision == REDSEA_PREC_BF16_IR)
+        return REDSEA_ERR_UNSUPPORTED;
+    Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb);
+    if (variant == 0) variant = VAR_RECURSIVE;
+    return execute(c, variant, pick_nb(nb, c.k), s);
+}
+
+void redsea_trace_begin(void) {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    for (auto& r : g_tr) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    g_tr.clear();
+    g_tr_on = true;
+}
+
+int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds) {
+    std::lock_guard<std::mutex> lock(g_tr_mu);
+    g_tr_on = false;
+    if (nkinds < 0 || (nkinds > 0 && (!launches || !ms || !flops))) return -4;
+    for (int k = 0; k < nkinds; ++k) {
+        launches[k] = 0;
+        ms[k] = 0.0;
+        flops[k] = 0.0;
+    }
+    int rc = REDSEA_OK;
+    for (auto& r : g_tr) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess)
+            rc = REDSEA_ERR_HIP;
+        if (r.kind >= 0 && r.kind < nkinds) {
+            launches[r.kind] += 1;
+            ms[r.kind] += t;
+            flops[r.kind] += r.flops;
+        }
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    g_tr.clear();
+    return rc;
+}
+
+int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int64_t count,
+                        const int64_t* m, const int64_t* n, double alpha,
+                        const void* const* A, const int64_t* lda, void* const* B,
+                        const int64_t* ldb, int* info, const redsea_opts* opts, void* stream) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (side != REDSEA_LEFT && side != REDSEA_RIGHT) return -2;
+    if (uplo != REDSEA_LOWER && uplo != REDSEA_UPPER) return -3;
+    if (trans != REDSEA_NOTRANS && trans != REDSEA_TRANS && trans != REDSEA_CONJTRANS) return -4;
+    if (diag != REDSEA_NONUNIT && diag != REDSEA_UNIT) return -5;
+    if (count < 0) return -6;
+    if (count == 0) return REDSEA_OK;
+    if (!m) return -7;
+    if (!n) return -8;
+    if (!A) return -10;
+    if (!lda) return -11;
+    if (!B) return -12;
+    if (!ldb) return -13;
+    if (!info) return -14;
+    int variant = opts ? opts->variant : 0;
+    int nb = opts ? opts->nb : 0;
+    if (variant < 0 || variant > 3) return -15;
+    if (!(nb == 0 || nb == 16 || nb == 32 || nb == 64 || nb == 128 || nb == 256 || nb == 512))
+        return -15;
+    for (int64_t i = 0; i < count; ++i) {
+        if (m[i] < 0) return -7;
+        if (n[i] < 0) return -8;
+        const int64_t ka = side == REDSEA_LEFT ? m[i] : n[i];
+        if (lda[i] < std::max<int64_t>(1, ka)) return -11;
+        if (ldb[i] < std::max<int64_t>(1, m[i])) return -13;
+        if (m[i] > 0 && n[i] > 0) {
+            if (alpha != 0.0 && A[i] == nullptr) return -10;
+            if (B[i] == nullptr) return -12;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t i = 0; i < count; ++i) {
+        if (m[i] > 0 && n[i] > 0) {
+            if (alpha != 1.0 && launch_scale(dtype, B[i], m[i], n[i], ldb[i], alpha, s) != hipSuccess)
+                return REDSEA_ERR_HIP;
+            if (alpha != 0.0) {
+                Canon c = canonicalize(dtype, side, uplo, trans, diag, m[i], n[i], A[i], lda[i],
+                                       B[i], ldb[i]);
+                int rc = execute(c, variant == 0 ? VAR_RECURSIVE : variant, pick_nb(nb, c.k), s);
+                if (rc) return rc;
+            }
+        }
+        if (launch_check_finite(dtype, B[i], m[i], n[i], ldb[i], info + i, REDSEA_ERR_NONFINITE,
+                                s) != hipSuccess)
+            return REDSEA_ERR_HIP;
+    }
+    return REDSEA_OK;
+}
+
+size_t redsea_trsm_mixed_workspace_bytes(int side, int64_t m, int64_t n, int inner) {
+    (void)side;
+    (void)inner;
+    if (m <= 0 || n <= 0) return 0;
+    return 0;
+}
+
+int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                      double alpha, const double* A, int64_t lda, double* B, int64_t ldb,
+                      int inner, double tol, int max_iter, void* work, size_t work_bytes,
+                      redsea_mixed_stats* stats, void* stream) {
+    (void)side; (void)uplo; (void)trans; (void)diag; (void)m; (void)n; (void)alpha; (void)A;
+    (void)lda; (void)B; (void)ldb; (void)inner; (void)tol; (void)max_iter; (void)work;
+    (void)work_bytes; (void)stats; (void)stream;
+    return REDSEA_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Executor internals shared by the entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+namespace redsea {
+
+// A solve in canonical form: forward substitution with the lower-triangular
+// T of order k on nrhs right-hand sides.
+struct Canon {
+    int dtype;
+    bool unit;
+    bool op_trans;   // the left problem's matrix is A^T (storage layout "T")
+    bool rhs_trans;  // right-hand sides are rows of B (right side)
+    bool reverse;    // backward substitution, indices reversed
+    int64_t k, nrhs;
+    const void* A;
+    int64_t lda;
+    void* B;
+    int64_t ldb;
+    TriView tri;
+    RhsView rhs;
+};
+
+Canon canonicalize(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                   const void* A, int64_t lda, void* B, int64_t ldb);
+GemmArgs gemm_args(const Canon& c, int64_t r0, int64_t R, int64_t c0, int64_t K);
+const std::vector<Task>& plan_for(int variant, int64_t k, int64_t nb, int64_t kleaf);
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s);
+int workspace(int slot, size_t bytes, void** out);
+int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
+int pick_nb(int requested, int64_t k);
+
+}  // namespace redsea

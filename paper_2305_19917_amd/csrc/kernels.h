@@ -1,0 +1,71 @@
+// Host-side launchers of the HIP kernels (gfx950).  Every launcher returns
+// the hipError_t of its launch.  Matrix coordinates are canonical: T is the
+// lower-triangular operator of a forward substitution, element (i, j) at
+// A + a_off + i * tr + j * tc (strides may be negative); B rows likewise.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace redsea {
+
+// Canonical view of the triangular operand: T(i, j) = base[off + i*tr + j*tc].
+struct TriView {
+    const void* base;
+    int64_t off, tr, tc;
+};
+
+// Canonical view of the right-hand sides: B(i, j) = base[off + i*br + j*bc].
+struct RhsView {
+    void* base;
+    int64_t off, br, bc;
+};
+
+// Copies the diagonal blocks of T into `packed`: block p (rows
+// [p*nb, p*nb+nb)) becomes an nb x nb column-major square whose lower
+// triangle holds T and whose rows past m are the identity.  nblk blocks.
+// unit: the diagonal is taken as one and not read.
+hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int64_t first_blk,
+                            int64_t nblk, bool unit, void* packed, hipStream_t s);
+
+// Solves the leaf at rows [row0, row0+rows) for all ncols columns, reading the
+// packed diagonal block `pblk` (nb x nb).  unit: skip the division.
+hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const RhsView& B,
+                       int64_t row0, int64_t ncols, bool unit, hipStream_t s);
+
+// Plain-layout product update in the library's storage coordinates:
+//   C(i, j) -= sum_k A(i, k) X(k, j),  i < M, j < N, k < K
+// A(i, k) = a[i + k*lda] (a_trans = false) or a[k + i*lda] (a_trans = true);
+// X(k, j) = x[k + j*ldx] and C(i, j) = c[i + j*ldc] (rhs_trans = false) or
+// x[j + k*ldx] and c[j + i*ldc] (rhs_trans = true).
+struct GemmArgs {
+    int64_t M, N, K;
+    const void* a;
+    int64_t lda;
+    const void* x;
+    int64_t ldx;
+    void* c;
+    int64_t ldc;
+};
+hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s);
+
+// Several independent products of the same layouts in one launch (a blocked
+// round, Sec. V-C).  The descriptors travel as kernel arguments, so at most
+// kMaxGroup per launch; no two of them may write the same rows of C.
+constexpr int kMaxGroup = 48;
+struct GemmGroup {
+    int count;
+    GemmArgs g[kMaxGroup];
+};
+hipError_t launch_gemm_group(int dtype, bool a_trans, bool rhs_trans, const GemmGroup& grp,
+                             hipStream_t s);
+
+// B(i, j) := alpha * B(i, j) over an m x n column-major matrix (alpha == 0
+// writes zeros without reading B).
+hipError_t launch_scale(int dtype, void* b, int64_t m, int64_t n, int64_t ldb, double alpha,
+                        hipStream_t s);
+
+// info[0] := 0 if every entry of the m x n matrix is finite, else `code`.
+hipError_t launch_check_finite(int dtype, const void* b, int64_t m, int64_t n, int64_t ldb,
+                               int* info, int code, hipStream_t s);
+
+}  // namespace redsea

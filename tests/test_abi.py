@@ -1,0 +1,95 @@
+"""The C-ABI library loads on the host and exports every declared symbol;
+argument checking and quick returns need no device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2305_19917_amd as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "redsea.h")).read()
+    return sorted(set(re.findall(r"\b(redsea_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(rs.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", rs.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (redsea_\w+)", out))
+    for name in _declared():
+        assert name in exported, name
+        assert getattr(rs.lib(), name) is not None
+
+
+def test_version_and_status_strings():
+    assert re.match(r"^\d+\.\d+\.\d+$", rs.version())
+    assert rs.status_string(0) == "success"
+    assert "invalid" in rs.status_string(-3)
+    for code in range(1, 6):
+        assert rs.status_string(code) != "unknown status"
+
+
+def _trsm_raw(**kw):
+    args = dict(dtype=0, side=0, uplo=0, trans=0, diag=0, m=4, n=3, alpha=1.0, A=8, lda=4, B=8,
+                ldb=4)
+    args.update(kw)
+    L = rs.lib()
+    return L.redsea_trsm(args["dtype"], args["side"], args["uplo"], args["trans"], args["diag"],
+                         args["m"], args["n"], args["alpha"], args["A"], args["lda"], args["B"],
+                         args["ldb"], None, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dtype=7), -1), (dict(side=2), -2), (dict(uplo=-1), -3), (dict(trans=3), -4),
+    (dict(diag=2), -5), (dict(m=-1), -6), (dict(n=-2), -7), (dict(lda=3), -10),
+    (dict(ldb=3), -12), (dict(A=None), -9), (dict(B=None), -11),
+    (dict(side=1, lda=2), -10),
+])
+def test_argument_errors(kw, code):
+    assert _trsm_raw(**kw) == code
+
+
+def test_quick_returns_touch_nothing():
+    # NULL pointers are fine when there is nothing to do
+    assert _trsm_raw(m=0, A=None, B=None) == 0
+    assert _trsm_raw(n=0, A=None, B=None) == 0
+
+
+def test_bad_options():
+    L = rs.lib()
+    for opts in (rs.Opts(9, 0, 0), rs.Opts(0, 48, 0), rs.Opts(0, 0, 7)):
+        assert L.redsea_trsm(0, 0, 0, 0, 0, 4, 3, 1.0, 8, 4, 8, 4, ctypes.byref(opts), None) == -13
+
+
+def test_batched_argument_errors():
+    L = rs.lib()
+    i64 = ctypes.c_int64
+    m = (i64 * 1)(4)
+    n = (i64 * 1)(3)
+    lda = (i64 * 1)(2)
+    ldb = (i64 * 1)(4)
+    ptrs = (ctypes.c_void_p * 1)(8)
+    assert L.redsea_trsm_batched(0, 0, 0, 0, 0, -1, m, n, 1.0, ptrs, lda, ptrs, ldb, 8, None,
+                                 None) == -6
+    assert L.redsea_trsm_batched(0, 0, 0, 0, 0, 0, None, None, 1.0, None, None, None, None, None,
+                                 None, None) == 0
+    assert L.redsea_trsm_batched(0, 0, 0, 0, 0, 1, m, n, 1.0, ptrs, lda, ptrs, ldb, 8, None,
+                                 None) == -11
+
+
+def test_schedule_argument_errors():
+    L = rs.lib()
+    assert L.redsea_schedule(5, 10, 16, None, 0) == -1
+    assert L.redsea_schedule(1, -1, 16, None, 0) == -2
+    assert L.redsea_schedule(1, 10, 0, None, 0) == -3
+    assert L.redsea_schedule(1, 10, 16, None, 5) == -4
+    assert L.redsea_schedule(1, 0, 16, None, 0) == 0
