@@ -175,6 +175,21 @@ const char* redsea_status_string(int code);
 int64_t redsea_schedule(int variant, int64_t m, int nb, int64_t* tasks, int64_t max_tasks);
 
 /*
+ * Product update C := C - op(A) op(X), the matrix-matrix product that the
+ * update stage of the split (Sec. IV, stage 2; Sec. V-A for many right-hand
+ * sides) performs, on the same MFMA kernels the solver uses.  op(A) is M x K:
+ * A[i + k*lda] (transa = 0) or A[k + i*lda] (transa = 1).  transx = 0: X is
+ * K x N at X[k + j*ldx] and C is M x N at C[i + j*ldc]; transx = 1: both are
+ * stored transposed, X[j + k*ldx] and C[j + i*ldc].  tile selects a kernel
+ * tile configuration (0 .. 9) or -1 for the default.  Argument numbers:
+ * dtype 1, transa 2, transx 3, M 4, N 5, K 6, A 7, lda 8, X 9, ldx 10, C 11,
+ * ldc 12, tile 13, stream 14.  Asynchronous on stream.
+ */
+int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, int64_t K,
+                       const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
+                       int64_t ldc, int tile, void* stream);
+
+/*
  * Kernel timing trace (HOST calls).  Between redsea_trace_begin() and
  * redsea_trace_end() every kernel the solver launches is bracketed by HIP
  * events on its stream.  redsea_trace_end() waits for those events and

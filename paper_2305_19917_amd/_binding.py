@@ -23,6 +23,7 @@ EXPORTS = (
     "redsea_status_string",
     "redsea_schedule",
     "redsea_version",
+    "redsea_gemm_update",
     "redsea_trace_begin",
     "redsea_trace_end",
 )
@@ -81,6 +82,9 @@ def lib() -> ctypes.CDLL:
     L.redsea_schedule.argtypes = [cint, i64, cint, ptr, i64]
     L.redsea_version.restype = ctypes.c_char_p
     L.redsea_version.argtypes = []
+    L.redsea_gemm_update.restype = cint
+    L.redsea_gemm_update.argtypes = [cint, cint, cint, i64, i64, i64, ptr, i64, ptr, i64, ptr, i64,
+                                     cint, ptr]
     L.redsea_trace_begin.restype = None
     L.redsea_trace_begin.argtypes = []
     L.redsea_trace_end.restype = cint
@@ -180,6 +184,23 @@ def trsm_mixed(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0
                                  ctypes.byref(st), _stream(stream))
     _check(rc)
     return st
+
+
+def gemm_update(A, X, C, transa=False, transx=False, tile: int = -1, stream=None):
+    """In place C := C - op(A) op(X) on the library's MFMA kernels.
+
+    With transx, X and C are passed as their transposes (row-major storage):
+    shapes are then X^T (N x K) and C^T (N x M)."""
+    if transx:
+        N, M = C.shape
+    else:
+        M, N = C.shape
+    K = A.shape[0] if transa else A.shape[1]
+    rc = lib().redsea_gemm_update(_dtype_code(C), int(bool(transa)), int(bool(transx)), M, N, K,
+                                  A.data_ptr(), _ld(A), X.data_ptr(), _ld(X), C.data_ptr(), _ld(C),
+                                  int(tile), _stream(stream))
+    _check(rc)
+    return C
 
 
 def mixed_workspace_bytes(side, m: int, n: int, inner: int) -> int:

@@ -51,7 +51,7 @@ def build(jobs: int = 0) -> str:
         if err.strip():
             sys.stderr.write(err + "\n")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + [o for o, _ in results]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

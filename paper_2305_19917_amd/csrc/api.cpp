@@ -223,18 +223,40 @@ hipError_t traced(int kind, double flops, hipStream_t s, F&& launch) {
 
 // ------------------------------------------------------------------ execution
 
-int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
-    const int64_t kleaf = std::min<int64_t>(nb, 64);
-    const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
-    const int64_t nblk = (c.k + kleaf - 1) / kleaf;
+namespace {
+
+std::mutex g_st_mu;
+std::map<int, std::vector<hipStream_t>> g_side;  // device -> helper streams
+
+// Helper streams of the current device (default priority, non-blocking),
+// created on first use and kept until the process ends.
+int side_streams(int count, hipStream_t* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return REDSEA_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_st_mu);
+    std::vector<hipStream_t>& v = g_side[dev];
+    while ((int)v.size() < count) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return REDSEA_ERR_HIP;
+        v.push_back(st);
+    }
+    for (int i = 0; i < count; ++i) out[i] = v[i];
+    return REDSEA_OK;
+}
+
+// The same solve restricted to right-hand sides [c0, c0 + w).
+Canon column_slice(const Canon& c, int64_t c0, int64_t w) {
+    Canon sub = c;
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
-    void* packed = nullptr;
-    int rc = workspace(0, (size_t)nblk * kleaf * kleaf * es, &packed);
-    if (rc) return rc;
-    if (traced(REDSEA_KERNEL_PACK, 0.0, s, [&] {
-            return launch_pack_diag(c.dtype, c.tri, c.k, (int)kleaf, 0, nblk, c.unit, packed, s);
-        }) != hipSuccess)
-        return REDSEA_ERR_HIP;
+    sub.nrhs = w;
+    sub.rhs.off += c0 * c.rhs.bc;
+    sub.B = (char*)c.B + es * (c.rhs_trans ? c0 : c0 * c.ldb);
+    return sub;
+}
+
+int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, const void* packed,
+              hipStream_t s) {
+    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
     size_t i = 0;
     while (i < tasks.size()) {
         const Task& t = tasks[i];
@@ -280,6 +302,61 @@ int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
         i = j;
     }
     return REDSEA_OK;
+}
+
+}  // namespace
+
+// Number of right-hand-side column groups solved concurrently on helper
+// streams: the leaf chain of one group then overlaps the products of the
+// others (the columns are independent systems).
+int column_groups(const Canon& c) {
+    const char* e = std::getenv("REDSEA_STREAMS");
+    int g = e ? std::atoi(e) : 1;
+    if (g < 1) g = 1;
+    if (g > 4) g = 4;
+    while (g > 1 && c.nrhs / g < 256) --g;
+    return g;
+}
+
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
+    const int64_t kleaf = std::min<int64_t>(nb, c.dtype == REDSEA_F64 ? 128 : 64);
+    const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
+    const int64_t nblk = (c.k + kleaf - 1) / kleaf;
+    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
+    void* packed = nullptr;
+    int rc = workspace(0, (size_t)nblk * kleaf * kleaf * es, &packed);
+    if (rc) return rc;
+    if (traced(REDSEA_KERNEL_PACK, 0.0, s, [&] {
+            return launch_pack_diag(c.dtype, c.tri, c.k, (int)kleaf, 0, nblk, c.unit, packed, s);
+        }) != hipSuccess)
+        return REDSEA_ERR_HIP;
+    const int groups = column_groups(c);
+    if (groups == 1) return run_tasks(c, tasks, kleaf, packed, s);
+
+    hipStream_t side[4];
+    if ((rc = side_streams(groups, side))) return rc;
+    hipEvent_t fork, join[4];
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return REDSEA_ERR_HIP;
+    if (hipEventRecord(fork, s) != hipSuccess) return REDSEA_ERR_HIP;
+    const int64_t w = (c.nrhs + groups - 1) / groups;
+    int made = 0;
+    for (int gi = 0; gi < groups && rc == REDSEA_OK; ++gi) {
+        const int64_t c0 = gi * w, cw = std::min(w, c.nrhs - c0);
+        if (cw <= 0) break;
+        if (hipStreamWaitEvent(side[gi], fork, 0) != hipSuccess) { rc = REDSEA_ERR_HIP; break; }
+        rc = run_tasks(column_slice(c, c0, cw), tasks, kleaf, packed, side[gi]);
+        if (hipEventCreateWithFlags(&join[gi], hipEventDisableTiming) != hipSuccess) {
+            rc = REDSEA_ERR_HIP;
+            break;
+        }
+        ++made;
+        if (hipEventRecord(join[gi], side[gi]) != hipSuccess ||
+            hipStreamWaitEvent(s, join[gi], 0) != hipSuccess)
+            rc = REDSEA_ERR_HIP;
+    }
+    for (int gi = 0; gi < made; ++gi) (void)hipEventDestroy(join[gi]);
+    (void)hipEventDestroy(fork);
+    return rc;
 }
 
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
@@ -404,6 +481,33 @@ int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds) {
     }
     g_tr.clear();
     return rc;
+}
+
+int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, int64_t K,
+                       const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
+                       int64_t ldc, int tile, void* stream) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (transa != 0 && transa != 1) return -2;
+    if (transx != 0 && transx != 1) return -3;
+    if (M < 0) return -4;
+    if (N < 0) return -5;
+    if (K < 0) return -6;
+    if (lda < std::max<int64_t>(1, transa ? K : M)) return -8;
+    if (ldx < std::max<int64_t>(1, transx ? N : K)) return -10;
+    if (ldc < std::max<int64_t>(1, transx ? N : M)) return -12;
+    if (tile < -1 || tile >= gemm_tile_count()) return -13;
+    if (M == 0 || N == 0 || K == 0) return REDSEA_OK;
+    if (!A) return -7;
+    if (!X) return -9;
+    if (!C) return -11;
+    GemmArgs g{M, N, K, A, lda, X, ldx, C, ldc};
+    const double fl = 2.0 * M * N * K;
+    hipStream_t s = (hipStream_t)stream;
+    return traced(REDSEA_KERNEL_GEMM, fl, s, [&] {
+               return launch_gemm(dtype, transa != 0, transx != 0, g, s, tile);
+           }) == hipSuccess
+               ? REDSEA_OK
+               : REDSEA_ERR_HIP;
 }
 
 int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int64_t count,

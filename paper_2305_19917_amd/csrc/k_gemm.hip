@@ -2,11 +2,13 @@
 //
 // This is the "gemm" task the paper offloads to the accelerator (Sec. V-A:
 // with many right-hand sides the update of stage 2 of Sec. IV becomes a
-// matrix-matrix product; the grey rectangles of Fig. 2-4).  Each workgroup of
-// four waves owns a 128 x 128 tile of C; each wave a 64 x 64 quarter held as
-// 4 x 4 MFMA accumulators of 16 x 16.  K advances in steps of 16 through a
-// double-buffered LDS stage: the next stage's global loads are in flight
-// while the current stage feeds the matrix cores.
+// matrix-matrix product; the grey rectangles of Fig. 2-4).  A workgroup owns a
+// BM x BN tile of C, split over WM x WN waves; each wave keeps its
+// (BM/WM) x (BN/WN) sub-tile as 16 x 16 MFMA accumulators.  K advances in
+// steps of BK through a double-buffered LDS stage: the next stage's global
+// loads are in flight while the current stage feeds the matrix cores.  The
+// tile configuration is a template parameter so the tuner can pick one per
+// shape.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -17,9 +19,6 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-constexpr int BM = 128, BN = 128, BK = 16, PAD = 2;
-constexpr int NT = 256;
 
 // Per-type MFMA 16x16x4 operations.  For both types lane l supplies
 // A[l % 16][l / 16] and X[l / 16][l % 16]; the 16 x 16 result lives in four
@@ -46,35 +45,48 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
-struct Smem {
-    T a[2][BK][BM + PAD];
-    T x[2][BK][BN + PAD];
+// Tile configuration: BM x BN tile, BK k-stage, WM x WN waves, MINB
+// workgroups per CU requested from the register allocator.
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int MINB_>
+struct Cfg {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, MINB = MINB_;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int FM = BM / WM / 16, FN = BN / WN / 16;  // fragments per wave
+    static constexpr int LA = BM * BK / NT, LX = BN * BK / NT;  // loads per thread
+    static constexpr int PAD = 2;
+    static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile");
+    static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "loads");
+    static_assert(BK % 4 == 0, "k");
 };
 
-template <typename T, bool AT, bool RT>
+template <typename T, typename C>
+struct Smem {
+    T a[2][C::BK][C::BM + C::PAD];
+    T x[2][C::BK][C::BN + C::PAD];
+};
+
+template <typename T, typename C, bool AT, bool RT>
 __device__ __forceinline__ void load_stage(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0,
-                                           int tid, T (&ra)[BM * BK / NT],
-                                           T (&rx)[BN * BK / NT]) {
+                                           int tid, T (&ra)[C::LA], T (&rx)[C::LX]) {
     const T* a = (const T*)g.a;
     const T* x = (const T*)g.x;
 #pragma unroll
-    for (int p = 0; p < BM * BK / NT; ++p) {
-        const int idx = p * NT + tid;
+    for (int p = 0; p < C::LA; ++p) {
+        const int idx = p * C::NT + tid;
         int kk, mm;
-        if (!AT) { kk = idx / BM; mm = idx % BM; }   // column of A: BM contiguous rows
-        else { mm = idx / BK; kk = idx % BK; }       // row of A^T storage: BK contiguous k
+        if (!AT) { kk = idx / C::BM; mm = idx % C::BM; }  // column of A: BM contiguous rows
+        else { mm = idx / C::BK; kk = idx % C::BK; }      // row of A^T storage: BK contiguous k
         const int64_t gi = m0 + mm, gk = k0 + kk;
         T v = T(0);
         if (gi < g.M && gk < g.K) v = AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda];
         ra[p] = v;
     }
 #pragma unroll
-    for (int p = 0; p < BN * BK / NT; ++p) {
-        const int idx = p * NT + tid;
+    for (int p = 0; p < C::LX; ++p) {
+        const int idx = p * C::NT + tid;
         int kk, jj;
-        if (!RT) { jj = idx / BK; kk = idx % BK; }   // column of X: BK contiguous k
-        else { kk = idx / BN; jj = idx % BN; }       // row of X^T storage: BN contiguous j
+        if (!RT) { jj = idx / C::BK; kk = idx % C::BK; }  // column of X: BK contiguous k
+        else { kk = idx / C::BN; jj = idx % C::BN; }      // row of X^T storage: BN contiguous j
         const int64_t gj = n0 + jj, gk = k0 + kk;
         T v = T(0);
         if (gj < g.N && gk < g.K) v = RT ? x[gj + gk * g.ldx] : x[gk + gj * g.ldx];
@@ -82,76 +94,76 @@ __device__ __forceinline__ void load_stage(const GemmArgs& g, int64_t m0, int64_
     }
 }
 
-template <typename T, bool AT, bool RT>
-__device__ __forceinline__ void store_stage(Smem<T>& sm, int buf, int tid,
-                                            const T (&ra)[BM * BK / NT],
-                                            const T (&rx)[BN * BK / NT]) {
+template <typename T, typename C, bool AT, bool RT>
+__device__ __forceinline__ void store_stage(Smem<T, C>& sm, int buf, int tid, const T (&ra)[C::LA],
+                                            const T (&rx)[C::LX]) {
 #pragma unroll
-    for (int p = 0; p < BM * BK / NT; ++p) {
-        const int idx = p * NT + tid;
+    for (int p = 0; p < C::LA; ++p) {
+        const int idx = p * C::NT + tid;
         int kk, mm;
-        if (!AT) { kk = idx / BM; mm = idx % BM; }
-        else { mm = idx / BK; kk = idx % BK; }
+        if (!AT) { kk = idx / C::BM; mm = idx % C::BM; }
+        else { mm = idx / C::BK; kk = idx % C::BK; }
         sm.a[buf][kk][mm] = ra[p];
     }
 #pragma unroll
-    for (int p = 0; p < BN * BK / NT; ++p) {
-        const int idx = p * NT + tid;
+    for (int p = 0; p < C::LX; ++p) {
+        const int idx = p * C::NT + tid;
         int kk, jj;
-        if (!RT) { jj = idx / BK; kk = idx % BK; }
-        else { kk = idx / BN; jj = idx % BN; }
+        if (!RT) { jj = idx / C::BK; kk = idx % C::BK; }
+        else { kk = idx / C::BN; jj = idx % C::BN; }
         sm.x[buf][kk][jj] = rx[p];
     }
 }
 
-template <typename T, bool AT, bool RT>
+template <typename T, typename C, bool AT, bool RT>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
-                                          Smem<T>& sm) {
+                                          Smem<T, C>& sm) {
     typedef typename Mfma<T>::acc_t acc_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % C::WM, wn = wave / C::WM;
+    constexpr int SM = C::BM / C::WM, SN = C::BN / C::WN;  // wave sub-tile
 
-    acc_t acc[4][4];
+    acc_t acc[C::FM][C::FN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < C::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < C::FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-    T ra[BM * BK / NT], rx[BN * BK / NT];
-    const int64_t nk = (g.K + BK - 1) / BK;
-    load_stage<T, AT, RT>(g, m0, n0, 0, tid, ra, rx);
-    store_stage<T, AT, RT>(sm, 0, tid, ra, rx);
+    T ra[C::LA], rx[C::LX];
+    const int64_t nk = (g.K + C::BK - 1) / C::BK;
+    load_stage<T, C, AT, RT>(g, m0, n0, 0, tid, ra, rx);
+    store_stage<T, C, AT, RT>(sm, 0, tid, ra, rx);
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int buf = (int)(kt & 1);
         const bool more = kt + 1 < nk;
-        if (more) load_stage<T, AT, RT>(g, m0, n0, (kt + 1) * BK, tid, ra, rx);
+        if (more) load_stage<T, C, AT, RT>(g, m0, n0, (kt + 1) * C::BK, tid, ra, rx);
 #pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks) {
+        for (int ks = 0; ks < C::BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            T fa[4], fx[4];
+            T fa[C::FM], fx[C::FN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = sm.a[buf][kr][wm * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < C::FM; ++i) fa[i] = sm.a[buf][kr][wm * SM + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) fx[j] = sm.x[buf][kr][wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < C::FN; ++j) fx[j] = sm.x[buf][kr][wn * SN + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < C::FM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mma(fa[i], fx[j], acc[i][j]);
+                for (int j = 0; j < C::FN; ++j) acc[i][j] = Mfma<T>::mma(fa[i], fx[j], acc[i][j]);
         }
-        if (more) store_stage<T, AT, RT>(sm, buf ^ 1, tid, ra, rx);
+        if (more) store_stage<T, C, AT, RT>(sm, buf ^ 1, tid, ra, rx);
         __syncthreads();
     }
 
     T* c = (T*)g.c;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < C::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < C::FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gi = m0 + wm * 64 + i * 16 + Mfma<T>::row(lane, r);
-                const int64_t gj = n0 + wn * 64 + j * 16 + (lane & 15);
+                const int64_t gi = m0 + wm * SM + i * 16 + Mfma<T>::row(lane, r);
+                const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
                 if (gi < g.M && gj < g.N) {
                     T* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
                     *p = *p - acc[i][j][r];
@@ -159,31 +171,168 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
             }
 }
 
-template <typename T, bool AT, bool RT>
-__global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g) {
-    __shared__ Smem<T> sm;
-    const int64_t tiles_m = (g.M + BM - 1) / BM;
-    const int64_t tile = blockIdx.x;
-    gemm_tile<T, AT, RT>(g, (tile % tiles_m) * BM, (tile / tiles_m) * BN, sm);
+// Workgroups are dispatched round-robin over the eight XCDs (each with its
+// own L2).  The launch index is remapped so that every XCD receives one
+// contiguous range of logical tiles, and logical tiles walk bands of GM
+// row-tiles along N, so an XCD's resident workgroups share A row panels and
+// X column panels in its L2.
+__device__ __forceinline__ void tile_coords(int64_t tiles_m, int64_t tiles_n, int64_t& tm,
+                                            int64_t& tn) {
+    constexpr int64_t kXcd = 8, GM = 8;
+    const int64_t nwg = (int64_t)gridDim.x;
+    int64_t bid = blockIdx.x;
+    if (nwg % kXcd == 0) bid = (bid % kXcd) * (nwg / kXcd) + bid / kXcd;
+    const int64_t band = GM * tiles_n;
+    const int64_t first = (bid / band) * GM;
+    const int64_t gsz = tiles_m - first < GM ? tiles_m - first : GM;
+    const int64_t r = bid % band;
+    tm = first + r % gsz;
+    tn = r / gsz;
 }
 
-template <typename T, bool AT, bool RT>
-__global__ __launch_bounds__(NT) void gemm_group_kernel(GemmGroup grp, int64_t tiles_m_max) {
-    __shared__ Smem<T> sm;
+template <typename T, typename C, bool AT, bool RT>
+__global__ __launch_bounds__(C::NT, C::MINB) void gemm_kernel(GemmArgs g) {
+    __shared__ Smem<T, C> sm;
+    const int64_t tiles_m = (g.M + C::BM - 1) / C::BM, tiles_n = (g.N + C::BN - 1) / C::BN;
+    int64_t tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    gemm_tile<T, C, AT, RT>(g, tm * C::BM, tn * C::BN, sm);
+}
+
+template <typename T, typename C, bool AT, bool RT>
+__global__ __launch_bounds__(C::NT, C::MINB) void gemm_group_kernel(GemmGroup grp,
+                                                                    int64_t tiles_m_max) {
+    __shared__ Smem<T, C> sm;
     const GemmArgs& g = grp.g[blockIdx.y];
     const int64_t tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
-    if (tm * BM >= g.M || tn * BN >= g.N) return;  // uniform over the workgroup
-    gemm_tile<T, AT, RT>(g, tm * BM, tn * BN, sm);
+    if (tm * C::BM >= g.M || tn * C::BN >= g.N) return;  // uniform over the workgroup
+    gemm_tile<T, C, AT, RT>(g, tm * C::BM, tn * C::BN, sm);
 }
 
-template <typename T, bool AT, bool RT>
-hipError_t gemm_launch_t(const GemmArgs& g, hipStream_t s) {
+// Short-K product (the small updates near the leaves of the recursion).  For
+// K of a few hundred the double-buffered pipeline never reaches steady state
+// and the read of C at the end adds a second memory latency.  This kernel
+// reads its C tile first, stages K in chunks of KC through one LDS buffer and
+// keeps two workgroups per CU so one computes while the other loads.
+template <typename T, int BM, int BN, int KC, bool AT, bool RT>
+__global__ __launch_bounds__(256, 2) void gemm_shortk_kernel(GemmArgs g) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int WM = 2, WN = 2, SM = BM / WM, SN = BN / WN, FM = SM / 16, FN = SN / 16;
+    constexpr int NT = 256, LA = BM * KC / NT, LX = BN * KC / NT, PAD = 2;
+    __shared__ T As[KC][BM + PAD];
+    __shared__ T Xs[KC][BN + PAD];
+    const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+    int64_t tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    T* c = (T*)g.c;
+    const T* a = (const T*)g.a;
+    const T* x = (const T*)g.x;
+
+    T cv[FM][FN][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = m0 + wm * SM + i * 16 + Mfma<T>::row(lane, r);
+                const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
+                cv[i][j][r] = (gi < g.M && gj < g.N) ? (RT ? c[gj + gi * g.ldc] : c[gi + gj * g.ldc])
+                                                     : T(0);
+            }
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    for (int64_t k0 = 0; k0 < g.K; k0 += KC) {
+        T ra[LA], rx[LX];
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int idx = p * NT + tid;
+            int kk, mm;
+            if (!AT) { kk = idx / BM; mm = idx % BM; }
+            else { mm = idx / KC; kk = idx % KC; }
+            const int64_t gi = m0 + mm, gk = k0 + kk;
+            ra[p] = (gi < g.M && gk < g.K) ? (AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda]) : T(0);
+        }
+#pragma unroll
+        for (int p = 0; p < LX; ++p) {
+            const int idx = p * NT + tid;
+            int kk, jj;
+            if (!RT) { jj = idx / KC; kk = idx % KC; }
+            else { kk = idx / BN; jj = idx % BN; }
+            const int64_t gj = n0 + jj, gk = k0 + kk;
+            rx[p] = (gj < g.N && gk < g.K) ? (RT ? x[gj + gk * g.ldx] : x[gk + gj * g.ldx]) : T(0);
+        }
+        if (k0 > 0) __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int idx = p * NT + tid;
+            int kk, mm;
+            if (!AT) { kk = idx / BM; mm = idx % BM; }
+            else { mm = idx / KC; kk = idx % KC; }
+            As[kk][mm] = ra[p];
+        }
+#pragma unroll
+        for (int p = 0; p < LX; ++p) {
+            const int idx = p * NT + tid;
+            int kk, jj;
+            if (!RT) { jj = idx / KC; kk = idx % KC; }
+            else { kk = idx / BN; jj = idx % BN; }
+            Xs[kk][jj] = rx[p];
+        }
+        __syncthreads();
+        const int64_t krem = g.K - k0;
+        const int ksteps = krem >= KC ? KC / 4 : (int)((krem + 3) / 4);
+        for (int ks = 0; ks < ksteps; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            T fa[FM], fx[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) fa[i] = As[kr][wm * SM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) fx[j] = Xs[kr][wn * SN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::mma(fa[i], fx[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = m0 + wm * SM + i * 16 + Mfma<T>::row(lane, r);
+                const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
+                if (gi < g.M && gj < g.N) {
+                    T* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
+                    *p = cv[i][j][r] - acc[i][j][r];
+                }
+            }
+}
+
+template <typename T, int BM, int BN, int KC, bool AT, bool RT>
+hipError_t gemm_shortk_launch(const GemmArgs& g, hipStream_t s) {
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_kernel<T, AT, RT>), dim3((unsigned)tiles), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((gemm_shortk_kernel<T, BM, BN, KC, AT, RT>), dim3((unsigned)tiles),
+                       dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
-template <typename T, bool AT, bool RT>
+template <typename T, typename C, bool AT, bool RT>
+hipError_t gemm_launch_t(const GemmArgs& g, hipStream_t s) {
+    const int64_t tiles = ((g.M + C::BM - 1) / C::BM) * ((g.N + C::BN - 1) / C::BN);
+    hipLaunchKernelGGL((gemm_kernel<T, C, AT, RT>), dim3((unsigned)tiles), dim3(C::NT), 0, s, g);
+    return hipGetLastError();
+}
+
+template <typename T, typename C, bool AT, bool RT>
 hipError_t gemm_group_launch_t(const GemmGroup& grp, hipStream_t s) {
     int64_t max_m = 0, max_n = 0;
     for (int i = 0; i < grp.count; ++i) {
@@ -191,42 +340,101 @@ hipError_t gemm_group_launch_t(const GemmGroup& grp, hipStream_t s) {
         if (grp.g[i].N > max_n) max_n = grp.g[i].N;
     }
     if (max_m <= 0 || max_n <= 0) return hipSuccess;
-    const int64_t tm = (max_m + BM - 1) / BM, tn = (max_n + BN - 1) / BN;
-    hipLaunchKernelGGL((gemm_group_kernel<T, AT, RT>), dim3((unsigned)(tm * tn), (unsigned)grp.count),
-                       dim3(NT), 0, s, grp, tm);
+    const int64_t tm = (max_m + C::BM - 1) / C::BM, tn = (max_n + C::BN - 1) / C::BN;
+    hipLaunchKernelGGL((gemm_group_kernel<T, C, AT, RT>),
+                       dim3((unsigned)(tm * tn), (unsigned)grp.count), dim3(C::NT), 0, s, grp, tm);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t gemm_launch_any(bool at, bool rt, const GemmArgs& g, hipStream_t s) {
-    if (!at && !rt) return gemm_launch_t<T, false, false>(g, s);
-    if (at && !rt) return gemm_launch_t<T, true, false>(g, s);
-    if (!at && rt) return gemm_launch_t<T, false, true>(g, s);
-    return gemm_launch_t<T, true, true>(g, s);
+// Tile configurations (index = tile argument).
+typedef Cfg<128, 128, 16, 2, 2, 1> Tile0;  // 64x64 per wave
+typedef Cfg<128, 128, 16, 2, 2, 2> Tile1;  // same, two workgroups per CU
+typedef Cfg<128, 128, 32, 2, 2, 1> Tile2;  // deeper k-stage
+typedef Cfg<64, 64, 16, 2, 2, 2> Tile3;    // small tiles for short M
+typedef Cfg<64, 128, 16, 2, 2, 2> Tile4;   // short M, wide N
+typedef Cfg<256, 128, 16, 4, 2, 1> Tile5;  // eight waves
+typedef Cfg<64, 64, 16, 2, 2, 4> Tile6;    // small tiles, four workgroups per CU
+typedef Cfg<64, 128, 32, 2, 2, 1> Tile7;   // short M, wide N, deeper k-stage
+constexpr int kTiles = 10;  // 8: short-K 64x64, 9: short-K 32x64
+
+template <typename T, bool AT, bool RT>
+hipError_t gemm_by_tile(int tile, const GemmArgs& g, hipStream_t s) {
+    switch (tile) {
+        case 0: return gemm_launch_t<T, Tile0, AT, RT>(g, s);
+        case 1: return gemm_launch_t<T, Tile1, AT, RT>(g, s);
+        case 2: return gemm_launch_t<T, Tile2, AT, RT>(g, s);
+        case 3: return gemm_launch_t<T, Tile3, AT, RT>(g, s);
+        case 4: return gemm_launch_t<T, Tile4, AT, RT>(g, s);
+        case 5: return gemm_launch_t<T, Tile5, AT, RT>(g, s);
+        case 6: return gemm_launch_t<T, Tile6, AT, RT>(g, s);
+        case 7: return gemm_launch_t<T, Tile7, AT, RT>(g, s);
+        case 8: return gemm_shortk_launch<T, 64, 64, 64, AT, RT>(g, s);
+        case 9: return gemm_shortk_launch<T, 32, 64, 64, AT, RT>(g, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool AT, bool RT>
+hipError_t gemm_group_by_tile(int tile, const GemmGroup& grp, hipStream_t s) {
+    switch (tile) {
+        case 0: return gemm_group_launch_t<T, Tile0, AT, RT>(grp, s);
+        case 1: return gemm_group_launch_t<T, Tile1, AT, RT>(grp, s);
+        case 2: return gemm_group_launch_t<T, Tile2, AT, RT>(grp, s);
+        case 3: return gemm_group_launch_t<T, Tile3, AT, RT>(grp, s);
+        case 4: return gemm_group_launch_t<T, Tile4, AT, RT>(grp, s);
+        case 5: return gemm_group_launch_t<T, Tile5, AT, RT>(grp, s);
+        case 6: return gemm_group_launch_t<T, Tile6, AT, RT>(grp, s);
+        case 7: return gemm_group_launch_t<T, Tile7, AT, RT>(grp, s);
+        default: return gemm_group_launch_t<T, Tile3, AT, RT>(grp, s);
+    }
 }
 
 template <typename T>
-hipError_t gemm_group_any(bool at, bool rt, const GemmGroup& grp, hipStream_t s) {
-    if (!at && !rt) return gemm_group_launch_t<T, false, false>(grp, s);
-    if (at && !rt) return gemm_group_launch_t<T, true, false>(grp, s);
-    if (!at && rt) return gemm_group_launch_t<T, false, true>(grp, s);
-    return gemm_group_launch_t<T, true, true>(grp, s);
+hipError_t gemm_any(int tile, bool at, bool rt, const GemmArgs& g, hipStream_t s) {
+    if (!at && !rt) return gemm_by_tile<T, false, false>(tile, g, s);
+    if (at && !rt) return gemm_by_tile<T, true, false>(tile, g, s);
+    if (!at && rt) return gemm_by_tile<T, false, true>(tile, g, s);
+    return gemm_by_tile<T, true, true>(tile, g, s);
+}
+
+template <typename T>
+hipError_t gemm_group_any(int tile, bool at, bool rt, const GemmGroup& grp, hipStream_t s) {
+    if (!at && !rt) return gemm_group_by_tile<T, false, false>(tile, grp, s);
+    if (at && !rt) return gemm_group_by_tile<T, true, false>(tile, grp, s);
+    if (!at && rt) return gemm_group_by_tile<T, false, true>(tile, grp, s);
+    return gemm_group_by_tile<T, true, true>(tile, grp, s);
 }
 
 }  // namespace
 
-hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s) {
+int gemm_tile_count() { return kTiles; }
+
+// Default tile for a product shape, from a sweep of the configurations on
+// MI355X (FP64, N = 8192): eight-wave 256 x 128 tiles for long K, 64 x 64
+// tiles around K = 512, the short-K kernel below that.
+int gemm_default_tile(int dtype, int64_t M, int64_t N, int64_t K) {
+    (void)dtype;
+    (void)N;
+    if (K <= 160 && M <= 160) return 9;
+    if (M <= 768 || K <= 384) return 3;
+    return 5;
+}
+
+hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s,
+                       int tile) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
-    return dtype == 0 ? gemm_launch_any<double>(a_trans, rhs_trans, g, s)
-                      : gemm_launch_any<float>(a_trans, rhs_trans, g, s);
+    if (tile < 0) tile = gemm_default_tile(dtype, g.M, g.N, g.K);
+    return dtype == 0 ? gemm_any<double>(tile, a_trans, rhs_trans, g, s)
+                      : gemm_any<float>(tile, a_trans, rhs_trans, g, s);
 }
 
 hipError_t launch_gemm_group(int dtype, bool a_trans, bool rhs_trans, const GemmGroup& grp,
-                             hipStream_t s) {
+                             hipStream_t s, int tile) {
     if (grp.count <= 0) return hipSuccess;
     if (grp.count > kMaxGroup) return hipErrorInvalidValue;
-    return dtype == 0 ? gemm_group_any<double>(a_trans, rhs_trans, grp, s)
-                      : gemm_group_any<float>(a_trans, rhs_trans, grp, s);
+    if (tile < 0) tile = gemm_default_tile(dtype, grp.g[0].M, grp.g[0].N, grp.g[0].K);
+    return dtype == 0 ? gemm_group_any<double>(tile, a_trans, rhs_trans, grp, s)
+                      : gemm_group_any<float>(tile, a_trans, rhs_trans, grp, s);
 }
 
 }  // namespace redsea

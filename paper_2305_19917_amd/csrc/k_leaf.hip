@@ -72,6 +72,143 @@ __global__ __launch_bounds__(64) void leaf_kernel(const T* __restrict__ P, int r
         if (FULL || i < rows) bp[i * br] = b[i];
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// FP64 panel leaf on matrix cores.  A workgroup of four waves covers 64
+// right-hand-side columns, each wave 16 of them, and holds its NP x 16 slab of
+// B in MFMA accumulator layout: fragment f, register r of lane l is row
+// 16 f + l/16 + 4 r, column l % 16 (the v_mfma_f64_16x16x4f64 result
+// layout).  The panel is solved by 16-row diagonal blocks:
+//   1. the 16 x 16 block of each column is gathered into one lane (every
+//      lane of the column's four lane groups gets the whole column, through
+//      LDS) and solved there by substitution, one IEEE division per row;
+//   2. each lane keeps its own four rows of the result;
+//   3. every later 16-row fragment is updated on the matrix cores,
+//      frag_p -= L_ps X_s, whose B operand for k-slice kk is exactly register
+//      kk of the solved fragment, so no data moves for the update.
+template <int NP, bool UNIT, bool FULL>
+__global__ __launch_bounds__(256) void leaf_mfma_f64_kernel(const double* __restrict__ P, int rows,
+                                                            double* __restrict__ B, int64_t off,
+                                                            int64_t br, int64_t bc,
+                                                            int64_t ncols) {
+    constexpr int NF = NP / 16;
+    __shared__ __attribute__((aligned(16))) double Ls[NP * NP];
+    __shared__ double Xs[4][16][17];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+    {
+        // stage the packed triangle: batches of independent 16-byte loads, so
+        // their latencies overlap instead of adding up
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        constexpr int PER = NP * NP / 512;  // 16-byte pieces per thread
+        constexpr int BATCH = PER < 1 ? 1 : (PER < 8 ? PER : 8);
+        const v2d* P2 = (const v2d*)P;
+        v2d* L2 = (v2d*)Ls;
+        if (PER == 0) {
+            for (int idx = tid; idx < NP * NP; idx += 256) Ls[idx] = P[idx];
+        } else {
+#pragma unroll
+            for (int b0 = 0; b0 < PER; b0 += BATCH) {
+                v2d t[BATCH];
+#pragma unroll
+                for (int q = 0; q < BATCH; ++q) t[q] = P2[(b0 + q) * 256 + tid];
+#pragma unroll
+                for (int q = 0; q < BATCH; ++q) L2[(b0 + q) * 256 + tid] = t[q];
+            }
+        }
+    }
+    const int64_t col = (int64_t)blockIdx.x * 64 + w * 16 + c;
+    const bool colok = col < ncols;
+    double* bp = B + off + (colok ? col : 0) * bc;
+    v4d fr[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * f + g + 4 * r;
+            fr[f][r] = (colok && (FULL || row < rows)) ? bp[row * br] : 0.0;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NF; ++s) {
+        // 1. gather the 16 rows of this block for column c into every lane
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[w][g + 4 * r][c] = fr[s][r];
+        __syncthreads();
+        double y[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) y[i] = Xs[w][i][c];
+        // substitution on the 16 x 16 diagonal block (axpy order).  Column
+        // i+1 of the block is read from LDS while column i is applied, so
+        // the chain of a step is one division and one fused multiply-add.
+        const double* Lb = Ls + (16 * s) * NP + 16 * s;  // element (j, i) at Lb[i*NP + j]
+        double cur[16], nxt[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) cur[j] = Lb[j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i + 1 < 16) {
+#pragma unroll
+                for (int j = i + 1; j < 16; ++j) nxt[j] = Lb[(i + 1) * NP + j];
+            }
+            double x = y[i];
+            if (!UNIT) x = x / cur[i];
+            y[i] = x;
+#pragma unroll
+            for (int j = i + 1; j < 16; ++j) y[j] = __builtin_fma(-cur[j], x, y[j]);
+#pragma unroll
+            for (int j = i; j < 16; ++j) asm volatile("" : "+v"(y[j]));
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int j = i + 1; j < 16; ++j) cur[j] = nxt[j];
+        }
+        __syncthreads();
+        // 2. keep this lane's rows (g + 4r) of the solved block
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((i & 3) == g) Xs[w][i][c] = y[i];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fr[s][r] = Xs[w][g + 4 * r][c];
+        // 3. matrix-core update of the fragments below
+#pragma unroll
+        for (int p = s + 1; p < NF; ++p)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double a = -Ls[(16 * s + 4 * kk + g) * NP + 16 * p + c];
+                fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, fr[s][kk], fr[p], 0, 0, 0);
+            }
+    }
+    if (colok) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * f + g + 4 * r;
+                if (FULL || row < rows) bp[row * br] = fr[f][r];
+            }
+    }
+}
+
+template <int NP>
+hipError_t leaf_mfma_dispatch(const double* P, int64_t rows, double* B, int64_t off, int64_t br,
+                              int64_t bc, int64_t ncols, bool unit, hipStream_t s) {
+    dim3 grid((unsigned)((ncols + 63) / 64)), block(256);
+    const bool full = rows == NP;
+    if (unit && full)
+        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, true, true>), grid, block, 0, s, P,
+                           (int)rows, B, off, br, bc, ncols);
+    else if (unit)
+        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, true, false>), grid, block, 0, s, P,
+                           (int)rows, B, off, br, bc, ncols);
+    else if (full)
+        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, false, true>), grid, block, 0, s, P,
+                           (int)rows, B, off, br, bc, ncols);
+    else
+        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, false, false>), grid, block, 0, s, P,
+                           (int)rows, B, off, br, bc, ncols);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ B, int64_t m, int64_t n,
                                                     int64_t ldb, T alpha) {
@@ -148,9 +285,10 @@ hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const 
         const double* P = (const double*)pblk;
         double* b = (double*)B.base;
         switch (nb) {
-            case 16: return leaf_dispatch<double, 16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 32: return leaf_dispatch<double, 32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 64: return leaf_dispatch<double, 64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 16: return leaf_mfma_dispatch<16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 32: return leaf_mfma_dispatch<32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 64: return leaf_mfma_dispatch<64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 128: return leaf_mfma_dispatch<128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             default: return hipErrorInvalidValue;
         }
     } else {

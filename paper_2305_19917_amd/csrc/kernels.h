@@ -46,7 +46,11 @@ struct GemmArgs {
     void* c;
     int64_t ldc;
 };
-hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s);
+// tile < 0 picks the default tile configuration for the shape.
+hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s,
+                       int tile = -1);
+int gemm_tile_count();
+int gemm_default_tile(int dtype, int64_t M, int64_t N, int64_t K);
 
 // Several independent products of the same layouts in one launch (a blocked
 // round, Sec. V-C).  The descriptors travel as kernel arguments, so at most
@@ -57,7 +61,7 @@ struct GemmGroup {
     GemmArgs g[kMaxGroup];
 };
 hipError_t launch_gemm_group(int dtype, bool a_trans, bool rhs_trans, const GemmGroup& grp,
-                             hipStream_t s);
+                             hipStream_t s, int tile = -1);
 
 // B(i, j) := alpha * B(i, j) over an m x n column-major matrix (alpha == 0
 // writes zeros without reading B).

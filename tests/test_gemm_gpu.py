@@ -1,0 +1,82 @@
+"""GPU product update C := C - op(A) op(X) (redsea_gemm_update) on every tile
+configuration and storage layout, against an FP64 CPU product.
+
+Bar: |C_gpu - C_ref| <= 2 K u (|C| + |A||X|) elementwise (the standard
+dot-product error bound with a margin), and bitwise on integer data whose
+partial sums are exact."""
+import numpy as np
+import pytest
+
+import paper_2305_19917_amd as rs
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+U64, U32 = 2.0 ** -53, 2.0 ** -24
+TILES = list(range(10))
+
+
+def _run(A, X, C, transa, transx, tile, dtype):
+    # stored forms: op(A) is M x K; with transa the stored A is K x M
+    dA = rs.fortran_tensor((A.T if transa else A).astype(dtype))
+    dX = rs.fortran_tensor((X.T if transx else X).astype(dtype))
+    dC = rs.fortran_tensor((C.T if transx else C).astype(dtype))
+    rs.gemm_update(dA, dX, dC, transa=transa, transx=transx, tile=tile)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy().astype(np.float64)
+    return out.T if transx else out
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("transa,transx", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_update_random(tile, transa, transx):
+    for (M, N, K) in [(1, 1, 1), (37, 129, 5), (200, 300, 150), (64, 64, 64), (130, 70, 300)]:
+        r = synth.rng((30, M, N + K))
+        A = r.standard_normal((M, K))
+        X = r.standard_normal((K, N))
+        C = r.standard_normal((M, N))
+        got = _run(A, X, C, transa, transx, tile, np.float64)
+        ref = C - A @ X
+        bound = 2 * K * U64 * (np.abs(C) + np.abs(A) @ np.abs(X))
+        assert np.all(np.abs(got - ref) <= bound), (M, N, K)
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_update_integer_exact(tile, dtype):
+    M, N, K = 150, 90, 77
+    r = synth.rng((31, 0, 0))
+    A = r.integers(-4, 5, (M, K)).astype(np.float64)
+    X = r.integers(-4, 5, (K, N)).astype(np.float64)
+    C = r.integers(-100, 100, (M, N)).astype(np.float64)
+    for transa, transx in [(0, 0), (1, 1)]:
+        got = _run(A, X, C, transa, transx, tile, dtype)
+        assert np.array_equal(got, C - A @ X)
+
+
+def test_update_fp32_bound():
+    M, N, K = 257, 190, 333
+    r = synth.rng((32, 0, 0))
+    A = r.standard_normal((M, K)).astype(np.float32).astype(np.float64)
+    X = r.standard_normal((K, N)).astype(np.float32).astype(np.float64)
+    C = r.standard_normal((M, N)).astype(np.float32).astype(np.float64)
+    for tile in TILES:
+        got = _run(A, X, C, 0, 0, tile, np.float32)
+        ref = C - A @ X
+        bound = 2 * (K + 1) * U32 * (np.abs(C) + np.abs(A) @ np.abs(X))
+        assert np.all(np.abs(got - ref) <= bound), tile
+
+
+def test_update_leaves_outside_untouched():
+    M, N, K, ld = 50, 40, 30, 64
+    r = synth.rng((33, 0, 0))
+    A = r.standard_normal((M, K))
+    X = r.standard_normal((K, N))
+    Cbig = np.full((ld, N), 9.0, order="F")
+    Cbig[:M] = r.standard_normal((M, N))
+    dA, dX, dC = rs.fortran_tensor(A), rs.fortran_tensor(X), rs.fortran_tensor(Cbig)
+    for tile in TILES:
+        rs.gemm_update(dA, dX, dC[:M, :], tile=tile)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    assert np.all(out[M:] == 9.0)

@@ -223,3 +223,25 @@ def test_thin_n8192_nrhs1024_sampled(kind):
     rs.trsm(dA, dB, uplo=uplo, trans=trans, diag=diag)
     torch.cuda.synchronize()
     _sampled_check(A, dB, B, [0, 5, 511, 1023], uplo, trans, diag)
+
+
+@pytest.mark.parametrize("groups", ["2", "3", "4"])
+def test_column_groups_on_streams_bitwise(groups, monkeypatch):
+    """Solving column groups concurrently on helper streams changes no bit:
+    every column's arithmetic is the same sequence of operations."""
+    k, nrhs = 1000, 1500
+    L = synth.dominant_lower(k, (14, 0, 0))
+    B = synth.rhs_normal(k, nrhs, (14, 0, 1))
+    for variant, nb in [("recursive", 64), ("blocked", 128)]:
+        monkeypatch.setenv("REDSEA_STREAMS", "1")
+        X1 = gpu_solve(L, B, variant=variant, nb=nb)
+        monkeypatch.setenv("REDSEA_STREAMS", groups)
+        X2 = gpu_solve(L, B, variant=variant, nb=nb)
+        assert np.array_equal(X1, X2), (variant, groups)
+    # the right side splits rows of B into groups
+    Br = synth.rhs_normal(nrhs, k, (14, 0, 2))
+    monkeypatch.setenv("REDSEA_STREAMS", "1")
+    X1 = gpu_solve(L, Br, side=1, nb=64)
+    monkeypatch.setenv("REDSEA_STREAMS", groups)
+    X2 = gpu_solve(L, Br, side=1, nb=64)
+    assert np.array_equal(X1, X2)
