@@ -113,17 +113,41 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
  * (spec batching pattern; each system is the solve of Sec. IV).
  * m, n, lda, ldb: HOST arrays of `count` entries.  A, B: HOST arrays of
  * `count` DEVICE pointers.  info: DEVICE int array of `count` entries that
- * receives 0 or a positive per-system code (REDSEA_ERR_NONFINITE when the
- * system's result holds a non-finite value).  The return value is 0, the -i
- * code of the first invalid argument (for per-system arrays, i is the
- * argument position), or a runtime failure code.  Argument numbers: dtype 1,
- * side 2, uplo 3, trans 4, diag 5, count 6, m 7, n 8, alpha 9, A 10, lda 11,
- * B 12, ldb 13, info 14, opts 15, stream 16.
+ * receives 0 or REDSEA_ERR_NONFINITE for a system whose result holds a
+ * non-finite value.  Systems of order up to 1024 are solved together by one
+ * persistent launch (tasks of up to 16 right-hand sides, longest first);
+ * larger ones by the single-system path on the same stream.  The return
+ * value is 0, the -i code of the first invalid argument (for the per-system
+ * arrays, i is the array's position), or a runtime failure code.  Argument
+ * numbers: dtype 1, side 2, uplo 3, trans 4, diag 5, count 6, m 7, n 8,
+ * alpha 9, A 10, lda 11, B 12, ldb 13, info 14, opts 15, stream 16.  This
+ * one-shot form builds a plan, runs it and frees it, which waits for the
+ * device; repeated batches should use the plan calls below.
  */
 int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int64_t count,
                         const int64_t* m, const int64_t* n, double alpha,
                         const void* const* A, const int64_t* lda, void* const* B,
                         const int64_t* ldb, int* info, const redsea_opts* opts, void* stream);
+
+/*
+ * Batched plan: the host work of redsea_trsm_batched (argument checks,
+ * canonical descriptors, task order, one synchronous upload) done once, so
+ * that redsea_batched_plan_run() is kernel launches only and may be captured
+ * in a hipGraph and replayed.  The plan keeps the device pointers it was
+ * created with; the caller keeps those buffers alive and unchanged in shape.
+ * create: arguments 1-13 as in redsea_trsm_batched, opts 14, out 15 (HOST
+ * pointer receiving the plan).  run: plan 1, info 2 (DEVICE int[count]),
+ * stream 3; calls of one plan must not overlap in time.  destroy waits for
+ * the device and frees the plan (NULL is ignored).
+ */
+typedef struct redsea_batch_plan redsea_batch_plan;
+int redsea_batched_plan_create(int dtype, int side, int uplo, int trans, int diag, int64_t count,
+                               const int64_t* m, const int64_t* n, double alpha,
+                               const void* const* A, const int64_t* lda, void* const* B,
+                               const int64_t* ldb, const redsea_opts* opts,
+                               redsea_batch_plan** out);
+int redsea_batched_plan_run(redsea_batch_plan* plan, int* info, void* stream);
+void redsea_batched_plan_destroy(redsea_batch_plan* plan);
 
 /* Statistics of one mixed-precision solve (host struct). */
 typedef struct {

@@ -24,6 +24,9 @@ EXPORTS = (
     "redsea_schedule",
     "redsea_version",
     "redsea_gemm_update",
+    "redsea_batched_plan_create",
+    "redsea_batched_plan_run",
+    "redsea_batched_plan_destroy",
     "redsea_trace_begin",
     "redsea_trace_end",
 )
@@ -85,6 +88,16 @@ def lib() -> ctypes.CDLL:
     L.redsea_gemm_update.restype = cint
     L.redsea_gemm_update.argtypes = [cint, cint, cint, i64, i64, i64, ptr, i64, ptr, i64, ptr, i64,
                                      cint, ptr]
+    L.redsea_batched_plan_create.restype = cint
+    L.redsea_batched_plan_create.argtypes = [cint, cint, cint, cint, cint, i64, ctypes.POINTER(i64),
+                                             ctypes.POINTER(i64), dbl, ctypes.POINTER(ptr),
+                                             ctypes.POINTER(i64), ctypes.POINTER(ptr),
+                                             ctypes.POINTER(i64), ctypes.POINTER(Opts),
+                                             ctypes.POINTER(ptr)]
+    L.redsea_batched_plan_run.restype = cint
+    L.redsea_batched_plan_run.argtypes = [ptr, ptr, ptr]
+    L.redsea_batched_plan_destroy.restype = None
+    L.redsea_batched_plan_destroy.argtypes = [ptr]
     L.redsea_trace_begin.restype = None
     L.redsea_trace_begin.argtypes = []
     L.redsea_trace_end.restype = cint
@@ -169,6 +182,50 @@ def trsm_batched(As: Sequence, Bs: Sequence, info, side="L", uplo="L", trans="N"
                                    ms, ns, float(alpha), aps, ldas, bps, ldbs, info.data_ptr(),
                                    ctypes.byref(opts), _stream(stream))
     _check(rc)
+
+
+def _batch_arrays(As, Bs):
+    count = len(Bs)
+    i64 = ctypes.c_int64
+    return (count, (i64 * count)(*[b.shape[0] for b in Bs]), (i64 * count)(*[b.shape[1] for b in Bs]),
+            (ctypes.c_void_p * count)(*[a.data_ptr() for a in As]),
+            (i64 * count)(*[_ld(a) for a in As]),
+            (ctypes.c_void_p * count)(*[b.data_ptr() for b in Bs]),
+            (i64 * count)(*[_ld(b) for b in Bs]))
+
+
+class BatchPlan:
+    """A prepared batch (redsea_batched_plan_*): run() only launches kernels,
+    so it can be captured in a graph.  The tensors must stay alive."""
+
+    def __init__(self, As, Bs, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
+                 variant="auto", nb: int = 0):
+        self._keep = (list(As), list(Bs))
+        count, ms, ns, aps, ldas, bps, ldbs = _batch_arrays(As, Bs)
+        self.count = count
+        opts = Opts(VARIANT[variant], int(nb), 0)
+        h = ctypes.c_void_p()
+        dt = _dtype_code(Bs[0]) if count else 0
+        _check(lib().redsea_batched_plan_create(dt, SIDE[side], UPLO[uplo], TRANS[trans],
+                                                DIAG[diag], count, ms, ns, float(alpha), aps,
+                                                ldas, bps, ldbs, ctypes.byref(opts),
+                                                ctypes.byref(h)))
+        self._h = h
+
+    def run(self, info, stream=None):
+        _check(lib().redsea_batched_plan_run(self._h, info.data_ptr() if info is not None else None,
+                                             _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().redsea_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trsm_mixed(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0, inner: int = 0,

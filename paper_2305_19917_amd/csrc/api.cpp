@@ -14,6 +14,7 @@
 #include "../../include/redsea.h"
 #include "exec.h"
 #include "kernels.h"
+#include "mixed.h"
 #include "plan.h"
 
 namespace redsea {
@@ -113,12 +114,16 @@ GemmArgs gemm_args(const Canon& c, int64_t r0, int64_t R, int64_t c0, int64_t K)
     }
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
     GemmArgs g;
+    if (c.gemm_bf16) {
+        const char* a16 = (const char*)c.A16;
+        g.a = c.op_trans ? a16 + 2 * (K0 + R0 * c.lda) : a16 + 2 * (R0 + K0 * c.lda);
+    }
     g.M = R;
     g.N = c.nrhs;
     g.K = K;
     const char* a = (const char*)c.A;
     // M(i, j) = A[i + j*lda] (not transposed) or A[j + i*lda] (transposed)
-    g.a = c.op_trans ? a + es * (K0 + R0 * c.lda) : a + es * (R0 + K0 * c.lda);
+    if (!c.gemm_bf16) g.a = c.op_trans ? a + es * (K0 + R0 * c.lda) : a + es * (R0 + K0 * c.lda);
     g.lda = c.lda;
     char* b = (char*)c.B;
     if (!c.rhs_trans) {
@@ -274,7 +279,17 @@ int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, con
         // gather the products of this round
         size_t j = i;
         while (j < tasks.size() && tasks[j].kind == TASK_GEMM && tasks[j].round == t.round) ++j;
-        if (j - i == 1) {
+        if (c.gemm_bf16) {
+            for (size_t q = i; q < j; ++q) {
+                GemmArgs g = gemm_args(c, tasks[q].row0, tasks[q].rows, tasks[q].col0,
+                                       tasks[q].cols);
+                const double fl = 2.0 * g.M * g.N * g.K;
+                if (traced(REDSEA_KERNEL_GEMM, fl, s, [&] {
+                        return launch_gemm_bf16(c.op_trans, c.rhs_trans, g, s);
+                    }) != hipSuccess)
+                    return REDSEA_ERR_HIP;
+            }
+        } else if (j - i == 1) {
             GemmArgs g = gemm_args(c, t.row0, t.rows, t.col0, t.cols);
             const double fl = 2.0 * g.M * g.N * g.K;
             if (traced(REDSEA_KERNEL_GEMM, fl, s,
@@ -319,7 +334,7 @@ int column_groups(const Canon& c) {
 }
 
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
-    const int64_t kleaf = std::min<int64_t>(nb, c.dtype == REDSEA_F64 ? 128 : 64);
+    const int64_t kleaf = std::min<int64_t>(nb, 128);
     const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
     const int64_t nblk = (c.k + kleaf - 1) / kleaf;
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
@@ -436,12 +451,17 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
     if (precision < 0 || precision > 3) return -13;
     if (m == 0 || n == 0) return REDSEA_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (alpha != 0.0 && (precision == REDSEA_PREC_FP32_IR || precision == REDSEA_PREC_BF16_IR)) {
+        if (dtype != REDSEA_F64) return REDSEA_ERR_UNSUPPORTED;
+        const int inner = precision == REDSEA_PREC_FP32_IR ? 1 : 2;
+        return mixed_solve(side, uplo, trans, diag, m, n, alpha, (const double*)A, lda,
+                           (double*)B, ldb, inner, 1e-12, inner == 1 ? 5 : 10, nullptr, 0,
+                           nullptr, opts, s);
+    }
     if (alpha == 0.0 || alpha != 1.0) {
         if (launch_scale(dtype, B, m, n, ldb, alpha, s) != hipSuccess) return REDSEA_ERR_HIP;
         if (alpha == 0.0) return REDSEA_OK;
     }
-    if (precision == REDSEA_PREC_FP32_IR || precision == REDSEA_PREC_BF16_IR)
-        return REDSEA_ERR_UNSUPPORTED;
     Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb);
     if (variant == 0) variant = VAR_RECURSIVE;
     return execute(c, variant, pick_nb(nb, c.k), s);
@@ -508,76 +528,6 @@ int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, 
            }) == hipSuccess
                ? REDSEA_OK
                : REDSEA_ERR_HIP;
-}
-
-int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int64_t count,
-                        const int64_t* m, const int64_t* n, double alpha,
-                        const void* const* A, const int64_t* lda, void* const* B,
-                        const int64_t* ldb, int* info, const redsea_opts* opts, void* stream) {
-    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
-    if (side != REDSEA_LEFT && side != REDSEA_RIGHT) return -2;
-    if (uplo != REDSEA_LOWER && uplo != REDSEA_UPPER) return -3;
-    if (trans != REDSEA_NOTRANS && trans != REDSEA_TRANS && trans != REDSEA_CONJTRANS) return -4;
-    if (diag != REDSEA_NONUNIT && diag != REDSEA_UNIT) return -5;
-    if (count < 0) return -6;
-    if (count == 0) return REDSEA_OK;
-    if (!m) return -7;
-    if (!n) return -8;
-    if (!A) return -10;
-    if (!lda) return -11;
-    if (!B) return -12;
-    if (!ldb) return -13;
-    if (!info) return -14;
-    int variant = opts ? opts->variant : 0;
-    int nb = opts ? opts->nb : 0;
-    if (variant < 0 || variant > 3) return -15;
-    if (!(nb == 0 || nb == 16 || nb == 32 || nb == 64 || nb == 128 || nb == 256 || nb == 512))
-        return -15;
-    for (int64_t i = 0; i < count; ++i) {
-        if (m[i] < 0) return -7;
-        if (n[i] < 0) return -8;
-        const int64_t ka = side == REDSEA_LEFT ? m[i] : n[i];
-        if (lda[i] < std::max<int64_t>(1, ka)) return -11;
-        if (ldb[i] < std::max<int64_t>(1, m[i])) return -13;
-        if (m[i] > 0 && n[i] > 0) {
-            if (alpha != 0.0 && A[i] == nullptr) return -10;
-            if (B[i] == nullptr) return -12;
-        }
-    }
-    hipStream_t s = (hipStream_t)stream;
-    for (int64_t i = 0; i < count; ++i) {
-        if (m[i] > 0 && n[i] > 0) {
-            if (alpha != 1.0 && launch_scale(dtype, B[i], m[i], n[i], ldb[i], alpha, s) != hipSuccess)
-                return REDSEA_ERR_HIP;
-            if (alpha != 0.0) {
-                Canon c = canonicalize(dtype, side, uplo, trans, diag, m[i], n[i], A[i], lda[i],
-                                       B[i], ldb[i]);
-                int rc = execute(c, variant == 0 ? VAR_RECURSIVE : variant, pick_nb(nb, c.k), s);
-                if (rc) return rc;
-            }
-        }
-        if (launch_check_finite(dtype, B[i], m[i], n[i], ldb[i], info + i, REDSEA_ERR_NONFINITE,
-                                s) != hipSuccess)
-            return REDSEA_ERR_HIP;
-    }
-    return REDSEA_OK;
-}
-
-size_t redsea_trsm_mixed_workspace_bytes(int side, int64_t m, int64_t n, int inner) {
-    (void)side;
-    (void)inner;
-    if (m <= 0 || n <= 0) return 0;
-    return 0;
-}
-
-int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
-                      double alpha, const double* A, int64_t lda, double* B, int64_t ldb,
-                      int inner, double tol, int max_iter, void* work, size_t work_bytes,
-                      redsea_mixed_stats* stats, void* stream) {
-    (void)side; (void)uplo; (void)trans; (void)diag; (void)m; (void)n; (void)alpha; (void)A;
-    (void)lda; (void)B; (void)ldb; (void)inner; (void)tol; (void)max_iter; (void)work;
-    (void)work_bytes; (void)stats; (void)stream;
-    return REDSEA_ERR_UNSUPPORTED;
 }
 
 }  // extern "C"

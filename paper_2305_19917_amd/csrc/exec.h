@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "../../include/redsea.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -25,6 +26,11 @@ struct Canon {
     int64_t ldb;
     TriView tri;
     RhsView rhs;
+    // BF16 products (mixed precision): the products read the BF16 copy A16
+    // (same layout and leading dimension as A, which then is FP32) and round
+    // X to BF16 on load; leaves stay on A.
+    bool gemm_bf16 = false;
+    const void* A16 = nullptr;
 };
 
 Canon canonicalize(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
@@ -36,5 +42,9 @@ int workspace(int slot, size_t bytes, void** out);
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
 int pick_nb(int requested, int64_t k);
+int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
+                const double* A, int64_t lda, double* B, int64_t ldb, int inner, double tol,
+                int max_iter, void* work, size_t work_bytes, redsea_mixed_stats* stats,
+                const redsea_opts* opts, hipStream_t s);
 
 }  // namespace redsea

@@ -65,7 +65,7 @@ struct Smem {
     T x[2][C::BK][C::BN + C::PAD];
 };
 
-template <typename T, typename C, bool AT, bool RT>
+template <typename T, typename C, bool AT, bool RT, int TRI = 0, bool UNIT = false>
 __device__ __forceinline__ void load_stage(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0,
                                            int tid, T (&ra)[C::LA], T (&rx)[C::LX]) {
     const T* a = (const T*)g.a;
@@ -78,7 +78,11 @@ __device__ __forceinline__ void load_stage(const GemmArgs& g, int64_t m0, int64_
         else { mm = idx / C::BK; kk = idx % C::BK; }      // row of A^T storage: BK contiguous k
         const int64_t gi = m0 + mm, gk = k0 + kk;
         T v = T(0);
-        if (gi < g.M && gk < g.K) v = AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda];
+        const bool inside = TRI == 0 || (TRI == 1 ? gk <= gi : gk >= gi);
+        if (gi < g.M && gk < g.K && inside) {
+            if (TRI != 0 && UNIT && gi == gk) v = T(1);
+            else v = AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda];
+        }
         ra[p] = v;
     }
 #pragma unroll
@@ -115,9 +119,9 @@ __device__ __forceinline__ void store_stage(Smem<T, C>& sm, int buf, int tid, co
     }
 }
 
-template <typename T, typename C, bool AT, bool RT>
+template <typename T, typename C, bool AT, bool RT, int TRI = 0, bool UNIT = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
-                                          Smem<T, C>& sm) {
+                                          Smem<T, C>& sm, T alpha_c = T(1)) {
     typedef typename Mfma<T>::acc_t acc_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % C::WM, wn = wave / C::WM;
@@ -130,14 +134,22 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
         for (int j = 0; j < C::FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     T ra[C::LA], rx[C::LX];
-    const int64_t nk = (g.K + C::BK - 1) / C::BK;
-    load_stage<T, C, AT, RT>(g, m0, n0, 0, tid, ra, rx);
+    // k range: all of K, or for a triangular M only the stages that meet the
+    // triangle in rows [m0, m0 + BM)
+    int64_t kb = 0, ke = (g.K + C::BK - 1) / C::BK;
+    if (TRI == 1) {
+        const int64_t last = m0 + C::BM < g.K ? m0 + C::BM : g.K;
+        ke = (last + C::BK - 1) / C::BK;
+    } else if (TRI == 2) {
+        kb = m0 / C::BK;
+    }
+    load_stage<T, C, AT, RT, TRI, UNIT>(g, m0, n0, kb * C::BK, tid, ra, rx);
     store_stage<T, C, AT, RT>(sm, 0, tid, ra, rx);
     __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = (int)(kt & 1);
-        const bool more = kt + 1 < nk;
-        if (more) load_stage<T, C, AT, RT>(g, m0, n0, (kt + 1) * C::BK, tid, ra, rx);
+    for (int64_t kt = kb; kt < ke; ++kt) {
+        const int buf = (int)((kt - kb) & 1);
+        const bool more = kt + 1 < ke;
+        if (more) load_stage<T, C, AT, RT, TRI, UNIT>(g, m0, n0, (kt + 1) * C::BK, tid, ra, rx);
 #pragma unroll
         for (int ks = 0; ks < C::BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
@@ -166,7 +178,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
                 if (gi < g.M && gj < g.N) {
                     T* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    *p = *p - acc[i][j][r];
+                    *p = (TRI == 0 ? *p : alpha_c * *p) - acc[i][j][r];
                 }
             }
 }
@@ -325,6 +337,23 @@ hipError_t gemm_shortk_launch(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename C, bool AT, bool RT, int TRI, bool UNIT>
+__global__ __launch_bounds__(C::NT, C::MINB) void residual_kernel(GemmArgs g, double alpha) {
+    __shared__ Smem<double, C> sm;
+    const int64_t tiles_m = (g.M + C::BM - 1) / C::BM, tiles_n = (g.N + C::BN - 1) / C::BN;
+    int64_t tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    gemm_tile<double, C, AT, RT, TRI, UNIT>(g, tm * C::BM, tn * C::BN, sm, alpha);
+}
+
+template <typename C, bool AT, bool RT, int TRI, bool UNIT>
+hipError_t residual_launch(const GemmArgs& g, double alpha, hipStream_t s) {
+    const int64_t tiles = ((g.M + C::BM - 1) / C::BM) * ((g.N + C::BN - 1) / C::BN);
+    hipLaunchKernelGGL((residual_kernel<C, AT, RT, TRI, UNIT>), dim3((unsigned)tiles), dim3(C::NT),
+                       0, s, g, alpha);
+    return hipGetLastError();
+}
+
 template <typename T, typename C, bool AT, bool RT>
 hipError_t gemm_launch_t(const GemmArgs& g, hipStream_t s) {
     const int64_t tiles = ((g.M + C::BM - 1) / C::BM) * ((g.N + C::BN - 1) / C::BN);
@@ -405,7 +434,29 @@ hipError_t gemm_group_any(int tile, bool at, bool rt, const GemmGroup& grp, hipS
     return gemm_group_by_tile<T, true, true>(tile, grp, s);
 }
 
+template <bool AT, bool RT, int TRI>
+hipError_t residual_u(bool unit, const GemmArgs& g, double alpha, hipStream_t s) {
+    return unit ? residual_launch<Tile5, AT, RT, TRI, true>(g, alpha, s)
+                : residual_launch<Tile5, AT, RT, TRI, false>(g, alpha, s);
+}
+
+template <int TRI>
+hipError_t residual_t(bool at, bool rt, bool unit, const GemmArgs& g, double alpha, hipStream_t s) {
+    if (!at && !rt) return residual_u<false, false, TRI>(unit, g, alpha, s);
+    if (at && !rt) return residual_u<true, false, TRI>(unit, g, alpha, s);
+    if (!at && rt) return residual_u<false, true, TRI>(unit, g, alpha, s);
+    return residual_u<true, true, TRI>(unit, g, alpha, s);
+}
+
 }  // namespace
+
+hipError_t launch_residual(bool a_trans, bool rhs_trans, int tri, bool unit, double alpha,
+                           const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (tri == 1) return residual_t<1>(a_trans, rhs_trans, unit, g, alpha, s);
+    if (tri == 2) return residual_t<2>(a_trans, rhs_trans, unit, g, alpha, s);
+    return hipErrorInvalidValue;
+}
 
 int gemm_tile_count() { return kTiles; }
 

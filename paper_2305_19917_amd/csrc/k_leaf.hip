@@ -2,13 +2,12 @@
 //
 // The leaf is the "TS" task that the paper's models leave at the finest
 // granularity (Sec. V-A: the white triangles of the recursive model; the
-// same tasks appear in Sec. V-B and V-C).  Here it runs on the GPU: each
-// lane owns one right-hand-side column, keeps the column's nb entries in
-// registers and performs the forward substitution of Sec. IV on them (axpy
-// order: after unknown k is divided out, every later row is updated with it).
-// The triangle is uniform across the wave: it is copied once into LDS from a
-// packed canonical copy and read with broadcast loads.  The dependency chain
-// per unknown is one IEEE division followed by fused multiply-adds.
+// same tasks appear in Sec. V-B and V-C).  Here it runs on the GPU, by the
+// forward substitution of Sec. IV in axpy order (after unknown k is divided
+// out, every later row is updated with it), on a packed canonical copy of the
+// diagonal block staged in LDS.  FP32 data is solved by the same kernel: it
+// is widened to FP64 on load and rounded to FP32 on store, so an FP32 leaf is
+// at least as accurate as one computed in FP32.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -37,41 +36,6 @@ __global__ __launch_bounds__(256) void pack_diag_kernel(const T* __restrict__ A,
     }
 }
 
-// One wave per 64 columns.  rows <= NB; the packed block completes rows past
-// `rows` with the identity, so they stay zero and are not stored.  The
-// triangle is staged in LDS once per workgroup and read with broadcast loads
-// (every lane reads the same element).
-template <typename T, int NB, bool UNIT, bool FULL>
-__global__ __launch_bounds__(64) void leaf_kernel(const T* __restrict__ P, int rows,
-                                                  T* __restrict__ B, int64_t off, int64_t br,
-                                                  int64_t bc, int64_t ncols) {
-    __shared__ T Ls[NB * NB];
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 64) Ls[idx] = P[idx];
-    __syncthreads();
-    const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (col >= ncols) return;
-    T* bp = B + off + col * bc;
-    T b[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) b[i] = (FULL || i < rows) ? bp[i * br] : T(0);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        T x = b[k];
-        if (!UNIT) x = x / Ls[k + k * NB];
-        b[k] = x;
-#pragma unroll
-        for (int i = k + 1; i < NB; ++i) b[i] = __builtin_fma(-Ls[i + k * NB], x, b[i]);
-        // Keep the axpy order: every update of step k is materialised here,
-        // and no LDS read of a later step is hoisted above this point.
-#pragma unroll
-        for (int i = k; i < NB; ++i) asm volatile("" : "+v"(b[i]));
-        asm volatile("" ::: "memory");
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (FULL || i < rows) bp[i * br] = b[i];
-}
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // FP64 panel leaf on matrix cores.  A workgroup of four waves covers 64
@@ -86,46 +50,38 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 //   3. every later 16-row fragment is updated on the matrix cores,
 //      frag_p -= L_ps X_s, whose B operand for k-slice kk is exactly register
 //      kk of the solved fragment, so no data moves for the update.
-template <int NP, bool UNIT, bool FULL>
-__global__ __launch_bounds__(256) void leaf_mfma_f64_kernel(const double* __restrict__ P, int rows,
-                                                            double* __restrict__ B, int64_t off,
-                                                            int64_t br, int64_t bc,
-                                                            int64_t ncols) {
+template <typename TS, int NP, bool UNIT, bool FULL>
+__global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P, int rows,
+                                                        TS* __restrict__ B, int64_t off,
+                                                        int64_t br, int64_t bc, int64_t ncols) {
     constexpr int NF = NP / 16;
     __shared__ __attribute__((aligned(16))) double Ls[NP * NP];
     __shared__ double Xs[4][16][17];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
     {
-        // stage the packed triangle: batches of independent 16-byte loads, so
-        // their latencies overlap instead of adding up
-        typedef double v2d __attribute__((ext_vector_type(2)));
-        constexpr int PER = NP * NP / 512;  // 16-byte pieces per thread
-        constexpr int BATCH = PER < 1 ? 1 : (PER < 8 ? PER : 8);
-        const v2d* P2 = (const v2d*)P;
-        v2d* L2 = (v2d*)Ls;
-        if (PER == 0) {
-            for (int idx = tid; idx < NP * NP; idx += 256) Ls[idx] = P[idx];
-        } else {
+        // stage the packed triangle: batches of independent loads, so their
+        // latencies overlap instead of adding up
+        constexpr int PER = NP * NP / 256;  // elements per thread
+        constexpr int BATCH = PER < 16 ? PER : 16;
 #pragma unroll
-            for (int b0 = 0; b0 < PER; b0 += BATCH) {
-                v2d t[BATCH];
+        for (int b0 = 0; b0 < PER; b0 += BATCH) {
+            TS t[BATCH];
 #pragma unroll
-                for (int q = 0; q < BATCH; ++q) t[q] = P2[(b0 + q) * 256 + tid];
+            for (int q = 0; q < BATCH; ++q) t[q] = P[(b0 + q) * 256 + tid];
 #pragma unroll
-                for (int q = 0; q < BATCH; ++q) L2[(b0 + q) * 256 + tid] = t[q];
-            }
+            for (int q = 0; q < BATCH; ++q) Ls[(b0 + q) * 256 + tid] = (double)t[q];
         }
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + w * 16 + c;
     const bool colok = col < ncols;
-    double* bp = B + off + (colok ? col : 0) * bc;
+    TS* bp = B + off + (colok ? col : 0) * bc;
     v4d fr[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * f + g + 4 * r;
-            fr[f][r] = (colok && (FULL || row < rows)) ? bp[row * br] : 0.0;
+            fr[f][r] = (colok && (FULL || row < rows)) ? (double)bp[row * br] : 0.0;
         }
     __syncthreads();
 #pragma unroll
@@ -184,27 +140,27 @@ __global__ __launch_bounds__(256) void leaf_mfma_f64_kernel(const double* __rest
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * f + g + 4 * r;
-                if (FULL || row < rows) bp[row * br] = fr[f][r];
+                if (FULL || row < rows) bp[row * br] = (TS)fr[f][r];
             }
     }
 }
 
-template <int NP>
-hipError_t leaf_mfma_dispatch(const double* P, int64_t rows, double* B, int64_t off, int64_t br,
+template <typename TS, int NP>
+hipError_t leaf_mfma_dispatch(const TS* P, int64_t rows, TS* B, int64_t off, int64_t br,
                               int64_t bc, int64_t ncols, bool unit, hipStream_t s) {
     dim3 grid((unsigned)((ncols + 63) / 64)), block(256);
     const bool full = rows == NP;
     if (unit && full)
-        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, true, true>), grid, block, 0, s, P,
+        hipLaunchKernelGGL((leaf_mfma_kernel<TS, NP, true, true>), grid, block, 0, s, P,
                            (int)rows, B, off, br, bc, ncols);
     else if (unit)
-        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, true, false>), grid, block, 0, s, P,
+        hipLaunchKernelGGL((leaf_mfma_kernel<TS, NP, true, false>), grid, block, 0, s, P,
                            (int)rows, B, off, br, bc, ncols);
     else if (full)
-        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, false, true>), grid, block, 0, s, P,
+        hipLaunchKernelGGL((leaf_mfma_kernel<TS, NP, false, true>), grid, block, 0, s, P,
                            (int)rows, B, off, br, bc, ncols);
     else
-        hipLaunchKernelGGL((leaf_mfma_f64_kernel<NP, false, false>), grid, block, 0, s, P,
+        hipLaunchKernelGGL((leaf_mfma_kernel<TS, NP, false, false>), grid, block, 0, s, P,
                            (int)rows, B, off, br, bc, ncols);
     return hipGetLastError();
 }
@@ -241,26 +197,6 @@ __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__
     if (threadIdx.x == 0) info[0] = bad ? code : 0;
 }
 
-template <typename T, int NB>
-hipError_t leaf_dispatch(const T* P, int64_t rows, T* B, int64_t off, int64_t br, int64_t bc,
-                         int64_t ncols, bool unit, hipStream_t s) {
-    dim3 grid((unsigned)((ncols + 63) / 64)), block(64);
-    const bool full = rows == NB;
-    if (unit && full)
-        hipLaunchKernelGGL((leaf_kernel<T, NB, true, true>), grid, block, 0, s, P, (int)rows, B,
-                           off, br, bc, ncols);
-    else if (unit)
-        hipLaunchKernelGGL((leaf_kernel<T, NB, true, false>), grid, block, 0, s, P, (int)rows, B,
-                           off, br, bc, ncols);
-    else if (full)
-        hipLaunchKernelGGL((leaf_kernel<T, NB, false, true>), grid, block, 0, s, P, (int)rows, B,
-                           off, br, bc, ncols);
-    else
-        hipLaunchKernelGGL((leaf_kernel<T, NB, false, false>), grid, block, 0, s, P, (int)rows,
-                           B, off, br, bc, ncols);
-    return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int64_t first_blk,
@@ -285,19 +221,22 @@ hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const 
         const double* P = (const double*)pblk;
         double* b = (double*)B.base;
         switch (nb) {
-            case 16: return leaf_mfma_dispatch<16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 32: return leaf_mfma_dispatch<32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 64: return leaf_mfma_dispatch<64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 128: return leaf_mfma_dispatch<128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 16: return leaf_mfma_dispatch<double, 16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 32: return leaf_mfma_dispatch<double, 32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 64: return leaf_mfma_dispatch<double, 64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 128:
+                return leaf_mfma_dispatch<double, 128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             default: return hipErrorInvalidValue;
         }
     } else {
         const float* P = (const float*)pblk;
         float* b = (float*)B.base;
         switch (nb) {
-            case 16: return leaf_dispatch<float, 16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 32: return leaf_dispatch<float, 32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
-            case 64: return leaf_dispatch<float, 64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 16: return leaf_mfma_dispatch<float, 16>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 32: return leaf_mfma_dispatch<float, 32>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 64: return leaf_mfma_dispatch<float, 64>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+            case 128:
+                return leaf_mfma_dispatch<float, 128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             default: return hipErrorInvalidValue;
         }
     }

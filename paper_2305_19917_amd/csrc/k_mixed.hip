@@ -1,0 +1,299 @@
+// Kernels of the mixed-precision solve with FP64 iterative refinement:
+// precision conversions, per-right-hand-side norms, the FP64 correction
+// update, and the BF16 product update (BF16 operands, FP32 accumulation) on
+// the gfx950 v_mfma_f32_16x16x32_bf16 matrix instruction.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "mixed.h"
+
+namespace redsea {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ conversions
+
+// dst (k x k, ld = k) := stored triangle of src (uplo) rounded to nearest
+// even; the other triangle is zero and a unit diagonal is one (neither is
+// read by the solver).  BF16 goes FP64 -> FP32 -> BF16, rounding to nearest
+// even at each step.
+template <typename TO>
+__global__ __launch_bounds__(256) void convert_tri_kernel(const double* __restrict__ src,
+                                                          int64_t lda, int64_t k, int uplo,
+                                                          int unit, TO* __restrict__ dst) {
+    const int64_t total = k * k;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % k, j = idx / k;
+        float v = 0.f;
+        if (i == j) v = unit ? 1.f : (float)src[i + j * lda];
+        else if ((uplo == 0 && i > j) || (uplo == 1 && i < j)) v = (float)src[i + j * lda];
+        dst[idx] = (TO)v;
+    }
+}
+
+// B32 := RN32(scale_r * B) over an m x n matrix; scale_r is the inverse
+// norm of the right-hand side the entry belongs to (its column for the left
+// side, its row for the right side), or one when inv is null.
+__global__ __launch_bounds__(256) void scale_to_f32_kernel(const double* __restrict__ src,
+                                                           int64_t ld, int64_t m, int64_t n,
+                                                           const double* __restrict__ inv,
+                                                           int rhs_rows, double alpha,
+                                                           float* __restrict__ dst, int64_t ldd) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % m, j = idx / m;
+        double v = alpha * src[i + j * ld];
+        if (inv) v *= inv[rhs_rows ? i : j];
+        dst[i + j * ldd] = (float)v;
+    }
+}
+
+// X := (scale ? X : 0) + s_r * D with s_r the norm of the entry's right-hand
+// side (one when s is null), in FP64.
+__global__ __launch_bounds__(256) void update_kernel(double* __restrict__ x, int64_t ldx,
+                                                     int64_t m, int64_t n,
+                                                     const float* __restrict__ d, int64_t ldd,
+                                                     const double* __restrict__ s, int rhs_rows,
+                                                     int accumulate) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % m, j = idx / m;
+        double v = (double)d[i + j * ldd];
+        if (s) v *= s[rhs_rows ? i : j];
+        double* p = x + i + j * ldx;
+        *p = accumulate ? *p + v : v;
+    }
+}
+
+// dst := alpha * src (m x n, FP64).
+__global__ __launch_bounds__(256) void copy_scaled_kernel(const double* __restrict__ src,
+                                                          int64_t lds, int64_t m, int64_t n,
+                                                          double alpha, double* __restrict__ dst,
+                                                          int64_t ldd) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t i = idx % m, j = idx / m;
+        const double v = src[i + j * lds];
+        dst[i + j * ldd] = alpha == 1.0 ? v : alpha * v;
+    }
+}
+
+// ------------------------------------------------------------------ norms
+
+// out[r] = max |entry| over right-hand side r (max is order independent, so
+// the result does not depend on the reduction order).  Columns (left side):
+// one workgroup per column, LDS reduction.  Rows (right side): one thread per
+// row, consecutive threads on consecutive rows.
+__global__ __launch_bounds__(256) void colmax_kernel(const double* __restrict__ a, int64_t ld,
+                                                     int64_t m, int64_t n, double scale,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    const int64_t j = blockIdx.x;
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) {
+        const double v = fabs(scale * a[i + j * ld]);
+        mx = (v > mx || v != v) ? v : mx;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            if (o > red[threadIdx.x] || o != o) red[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+__global__ __launch_bounds__(256) void rowmax_kernel(const double* __restrict__ a, int64_t ld,
+                                                     int64_t m, int64_t n, double scale,
+                                                     double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    double mx = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double v = fabs(scale * a[i + j * ld]);
+        mx = (v > mx || v != v) ? v : mx;
+    }
+    out[i] = mx;
+}
+
+// out[i] = sum_j |M(i, j)| over the triangle of M (row sums; the infinity
+// norm of M is their maximum).  M(i, j) = a[i + j*lda] or a[j + i*lda].
+__global__ __launch_bounds__(256) void tri_rowsum_kernel(const double* __restrict__ a, int64_t lda,
+                                                         int64_t k, int a_trans, int lower,
+                                                         int unit, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= k) return;
+    double sum = 0.0;
+    const int64_t j0 = lower ? 0 : i, j1 = lower ? i + 1 : k;
+    for (int64_t j = j0; j < j1; ++j) {
+        const double v = (j == i && unit) ? 1.0 : (a_trans ? a[j + i * lda] : a[i + j * lda]);
+        sum += fabs(v);
+    }
+    out[i] = sum;
+}
+
+// ------------------------------------------------------------------ BF16 product
+
+// C (FP32) -= A (BF16) X (FP32 rounded to BF16 on load), FP32 accumulation.
+// 128 x 128 tiles, four waves of 64 x 64, K in stages of 32.  Both operands
+// are kept k-contiguous in LDS so each lane reads its eight k values of an
+// MFMA operand with one 16-byte load.
+constexpr int HB_BM = 128, HB_BN = 128, HB_BK = 32, HB_PAD = 8;
+
+template <bool AT, bool RT>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[HB_BM][HB_BK + HB_PAD];
+    __shared__ __attribute__((aligned(16))) __bf16 Xs[HB_BN][HB_BK + HB_PAD];
+    const int64_t tiles_m = (g.M + HB_BM - 1) / HB_BM;
+    const int64_t m0 = (blockIdx.x % tiles_m) * HB_BM, n0 = (blockIdx.x / tiles_m) * HB_BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1, gq = lane >> 4, cc = lane & 15;
+    const __bf16* a = (const __bf16*)g.a;
+    const float* x = (const float*)g.x;
+    float* c = (float*)g.c;
+    v4f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const __bf16 zero = (__bf16)0.f;
+    for (int64_t k0 = 0; k0 < g.K; k0 += HB_BK) {
+        // A tile: BM x BK
+#pragma unroll 4
+        for (int p = 0; p < HB_BM * HB_BK / 256; ++p) {
+            const int idx = p * 256 + tid;
+            int mm, kk;
+            if (!AT) { mm = idx % HB_BM; kk = idx / HB_BM; }
+            else { kk = idx % HB_BK; mm = idx / HB_BK; }
+            const int64_t gi = m0 + mm, gk = k0 + kk;
+            As[mm][kk] = (gi < g.M && gk < g.K) ? (AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda]) : zero;
+        }
+#pragma unroll 4
+        for (int p = 0; p < HB_BN * HB_BK / 256; ++p) {
+            const int idx = p * 256 + tid;
+            int jj, kk;
+            if (!RT) { kk = idx % HB_BK; jj = idx / HB_BK; }
+            else { jj = idx % HB_BN; kk = idx / HB_BN; }
+            const int64_t gj = n0 + jj, gk = k0 + kk;
+            const float v = (gj < g.N && gk < g.K) ? (RT ? x[gj + gk * g.ldx] : x[gk + gj * g.ldx]) : 0.f;
+            Xs[jj][kk] = (__bf16)v;
+        }
+        __syncthreads();
+        v8bf fa[4], fx[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[i] = *(const v8bf*)&As[wm * 64 + i * 16 + cc][8 * gq];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fx[j] = *(const v8bf*)&Xs[wn * 64 + j * 16 + cc][8 * gq];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fx[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = m0 + wm * 64 + i * 16 + 4 * gq + r;
+                const int64_t gj = n0 + wn * 64 + j * 16 + cc;
+                if (gi < g.M && gj < g.N) {
+                    float* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
+                    *p = *p - acc[i][j][r];
+                }
+            }
+}
+
+unsigned grid_for(int64_t total) {
+    int64_t b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_convert_tri(int to_bf16, const double* a, int64_t lda, int64_t k, int uplo,
+                              bool unit, void* dst, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    if (to_bf16)
+        hipLaunchKernelGGL(convert_tri_kernel<__bf16>, dim3(grid_for(k * k)), dim3(256), 0, s, a,
+                           lda, k, uplo, unit ? 1 : 0, (__bf16*)dst);
+    else
+        hipLaunchKernelGGL(convert_tri_kernel<float>, dim3(grid_for(k * k)), dim3(256), 0, s, a,
+                           lda, k, uplo, unit ? 1 : 0, (float*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_to_f32(const double* src, int64_t ld, int64_t m, int64_t n,
+                               const double* inv, bool rhs_rows, double alpha, float* dst,
+                               int64_t ldd, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(grid_for(m * n)), dim3(256), 0, s, src, ld, m, n,
+                       inv, rhs_rows ? 1 : 0, alpha, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(double* x, int64_t ldx, int64_t m, int64_t n, const float* d, int64_t ldd,
+                         const double* scale, bool rhs_rows, bool accumulate, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(update_kernel, dim3(grid_for(m * n)), dim3(256), 0, s, x, ldx, m, n, d, ldd,
+                       scale, rhs_rows ? 1 : 0, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_scaled(const double* src, int64_t lds, int64_t m, int64_t n, double alpha,
+                              double* dst, int64_t ldd, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_scaled_kernel, dim3(grid_for(m * n)), dim3(256), 0, s, src, lds, m, n,
+                       alpha, dst, ldd);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_max(const double* a, int64_t ld, int64_t m, int64_t n, bool rhs_rows,
+                          double scale, double* out, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (!rhs_rows)
+        hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)n), dim3(256), 0, s, a, ld, m, n, scale,
+                           out);
+    else
+        hipLaunchKernelGGL(rowmax_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, ld,
+                           m, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_rowsum(const double* a, int64_t lda, int64_t k, bool a_trans, bool lower,
+                             bool unit, double* out, hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tri_rowsum_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, a,
+                       lda, k, a_trans ? 1 : 0, lower ? 1 : 0, unit ? 1 : 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16(bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+    const int64_t tiles = ((g.M + HB_BM - 1) / HB_BM) * ((g.N + HB_BN - 1) / HB_BN);
+    if (!a_trans && !rhs_trans)
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    else if (a_trans && !rhs_trans)
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    else if (!a_trans && rhs_trans)
+        hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+}  // namespace redsea

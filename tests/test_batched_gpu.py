@@ -1,0 +1,129 @@
+"""Batched persistent solve (redsea_trsm_batched and the plan API) against the
+oracle, system by system; graph capture and replay of a plan."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2305_19917_amd as rs
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _make(count, key, n_range=(32, 1024), nrhs_range=(1, 256), side=0, uplo=0, trans=0, diag=0):
+    ns, ks = synth.batch_shapes(count, key, n_range, nrhs_range)
+    As, Bs = [], []
+    for i, (n, k) in enumerate(zip(ns, ks)):
+        L = synth.unit_lower(int(n), (3, i, 0)) if diag else synth.dominant_lower(int(n), (3, i, 0))
+        A = np.asfortranarray(L if uplo == 0 else L.T)
+        B = synth.rhs_normal(*((int(n), int(k)) if side == 0 else (int(k), int(n))), key=(3, i, 1))
+        As.append(A)
+        Bs.append(B)
+    return As, Bs
+
+
+def _run(As, Bs, dtype=np.float64, **kw):
+    dAs = [rs.fortran_tensor(a.astype(dtype)) for a in As]
+    dBs = [rs.fortran_tensor(b.astype(dtype)) for b in Bs]
+    info = torch.full((len(Bs),), -7, dtype=torch.int32, device="cuda")
+    rs.trsm_batched(dAs, dBs, info, **kw)
+    torch.cuda.synchronize()
+    return [b.cpu().numpy().astype(np.float64) for b in dBs], info.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype,bound", [(np.float64, 1e-14), (np.float32, 5e-6)])
+def test_config3_shapes_per_system(dtype, bound):
+    As, Bs = _make(300, (3, 0, 2))
+    Xs, info = _run(As, Bs, dtype)
+    assert np.all(info == 0)
+    worst = 0.0
+    for A, B, X in zip(As, Bs, Xs):
+        A2, B2 = A.astype(dtype).astype(np.float64), B.astype(dtype).astype(np.float64)
+        eta = oracle.backward_error(0, 0, 0, 0, 1.0, A2, B2, X)
+        worst = max(worst, eta / A.shape[0])
+        assert eta <= bound * A.shape[0], (A.shape, B.shape, eta)
+    _say("batched", dtype.__name__, "worst eta/n", worst)
+
+
+@pytest.mark.parametrize("side,uplo,trans,diag", [(0, 0, 0, 0), (0, 1, 1, 0), (0, 1, 0, 1),
+                                                  (0, 0, 1, 0), (1, 0, 0, 0), (1, 1, 1, 1)])
+def test_integer_exact_flags(side, uplo, trans, diag):
+    As, Bs, Xt = [], [], []
+    shapes = [(1, 1), (5, 3), (16, 16), (17, 1), (100, 33), (257, 40), (1000, 7)]
+    for i, (k, r) in enumerate(shapes):
+        m, n = (k, r) if side == 0 else (r, k)
+        A, B, X = synth.integer_exact(m, n, (21, i, side), side, uplo, trans, diag)
+        As.append(A)
+        Bs.append(B)
+        Xt.append(X)
+    for dtype in (np.float64, np.float32):
+        Xs, info = _run(As, Bs, dtype, side=side, uplo=uplo, trans=trans, diag=diag)
+        assert np.all(info == 0)
+        for X, T in zip(Xs, Xt):
+            assert np.array_equal(X, T)
+
+
+def test_big_systems_and_empty_and_alpha():
+    As, Bs = _make(20, (3, 1, 2), n_range=(32, 300))
+    As.append(synth.dominant_lower(1500, (3, 99, 0)))    # above the panel limit
+    Bs.append(synth.rhs_normal(1500, 20, (3, 99, 1)))
+    As.append(synth.dominant_lower(10, (3, 98, 0)))      # no right-hand sides
+    Bs.append(np.zeros((10, 0), order="F"))
+    Xs, info = _run(As, Bs, alpha=-2.0)
+    assert np.all(info == 0)
+    for A, B, X in zip(As, Bs, Xs):
+        if B.size:
+            assert oracle.backward_error(0, 0, 0, 0, -2.0, A, B, X) <= 1e-14 * A.shape[0]
+
+
+def test_nonfinite_system_is_flagged():
+    As, Bs = _make(6, (3, 2, 2), n_range=(40, 200), nrhs_range=(2, 20))
+    Bs[3] = Bs[3].copy(order="F")
+    Bs[3][5, 0] = np.inf
+    _, info = _run(As, Bs)
+    assert info[3] == 4 and np.all(np.delete(info, 3) == 0)
+
+
+def test_run_to_run_bitwise_and_graph_replay():
+    As, Bs = _make(120, (3, 3, 2))
+    dAs = [rs.fortran_tensor(a) for a in As]
+    dB0 = [rs.fortran_tensor(b) for b in Bs]
+    dBs = [b.clone() for b in dB0]
+    dBs = [b.t().contiguous().t() if b.numel() else b for b in dBs]
+    info = torch.zeros(len(Bs), dtype=torch.int32, device="cuda")
+    plan = rs.BatchPlan(dAs, dBs)
+    plan.run(info)
+    torch.cuda.synchronize()
+    ref = [b.cpu().numpy() for b in dBs]
+    # second eager run from restored inputs is bitwise identical
+    for b, b0 in zip(dBs, dB0):
+        b.copy_(b0)
+    plan.run(info)
+    torch.cuda.synchronize()
+    assert all(np.array_equal(b.cpu().numpy(), r) for b, r in zip(dBs, ref))
+    # capture once, replay several times with eager restores in between
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    for b, b0 in zip(dBs, dB0):
+        b.copy_(b0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        plan.run(info, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for b, b0 in zip(dBs, dB0):
+            b.copy_(b0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(np.array_equal(b.cpu().numpy(), r) for b, r in zip(dBs, ref)), rep
+        assert int(info.abs().sum().item()) == 0
+    plan.close()

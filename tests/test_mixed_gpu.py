@@ -1,0 +1,134 @@
+"""Mixed precision with FP64 iterative refinement (redsea_trsm_mixed) against
+the oracle: normwise backward error <= 1e-12 after refinement, measured with
+the oracle's compensated residual; exact data needs no correction; the FP64
+fallback is taken when refinement cannot converge."""
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2305_19917_amd as rs
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kappa_family.json")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mixed(A, B, inner, side=0, uplo=0, trans=0, diag=0, alpha=1.0, tol=0.0, max_iter=0):
+    dA = rs.fortran_tensor(A)
+    dB = rs.fortran_tensor(B)
+    st = rs.trsm_mixed(dA, dB, side=side, uplo=uplo, trans=trans, diag=diag, alpha=alpha,
+                       inner=inner, tol=tol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    return dB.cpu().numpy(), st
+
+
+def _kappa_c(n):
+    tab = json.load(open(GOLDEN))
+    return [(e["target"], e["c"]) for e in tab["entries"] if e["n"] == n], tuple(tab["key"])
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="kappa table not generated")
+@pytest.mark.parametrize("inner", [1, 2])
+def test_kappa_family_reaches_1e12(inner):
+    n, nrhs = 2048, 96
+    cs, key = _kappa_c(n)
+    for target, c in cs:
+        L = synth.kappa_lower(n, c, key)
+        B = synth.rhs_normal(n, nrhs, (2, 0, 1))
+        X, st = mixed(L, B, inner)
+        eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X)
+        Xo = oracle.trsm_comp(0, 0, 0, 0, 1.0, L, B)
+        _say("kappa %.0e inner %d: iters %d fell_back %d eta(lib) %.2e eta(oracle) %.2e fwd %.2e"
+             % (target, inner, st.iterations, st.fell_back, st.eta, eta,
+                oracle.forward_error(X, Xo)))
+        assert eta <= 1e-12, (target, eta)
+
+
+@pytest.mark.parametrize("inner", [1, 2])
+def test_integer_exact_needs_no_correction(inner):
+    for side, uplo, trans, diag in [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 0, 1), (1, 1, 0, 0)]:
+        k, nrhs = 300, 40
+        m, n = (k, nrhs) if side == 0 else (nrhs, k)
+        A, B, Xt = synth.integer_exact(m, n, (15, side, uplo), side, uplo, trans, diag)
+        X, st = mixed(A, B, inner, side, uplo, trans, diag)
+        assert np.array_equal(X, Xt)
+        assert st.iterations == 0 and st.fell_back == 0
+
+
+@pytest.mark.parametrize("side,uplo,trans,diag", list(itertools.product([0, 1], [0, 1], [0, 1], [0, 1])))
+def test_all_flags_backward_error(side, uplo, trans, diag):
+    k, nrhs = 400, 30
+    L = synth.unit_lower(k, (16, k, 0)) if diag else synth.dominant_lower(k, (16, k, 0))
+    A = np.array(L if uplo == 0 else L.T, order="F")
+    B = synth.rhs_normal(*((k, nrhs) if side == 0 else (nrhs, k)), key=(16, k, 1))
+    for inner in (1, 2):
+        X, st = mixed(A, B, inner, side, uplo, trans, diag, alpha=-0.75)
+        eta = oracle.backward_error(side, uplo, trans, diag, -0.75, A, B, X)
+        assert eta <= 1e-12, (inner, eta, st.iterations, st.fell_back)
+
+
+def test_unreachable_tolerance_falls_back_to_fp64():
+    n, nrhs = 700, 20
+    L = synth.dominant_lower(n, (17, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (17, 0, 1))
+    X, st = mixed(L, B, 2, tol=1e-300, max_iter=3)
+    assert st.fell_back == 1
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * n
+    # the fallback equals the plain FP64 library solve bitwise
+    dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+    rs.trsm(dL, dB, variant="recursive", nb=128)
+    torch.cuda.synchronize()
+    assert np.array_equal(X, dB.cpu().numpy())
+
+
+def test_caller_workspace_and_size_query():
+    n, nrhs = 500, 64
+    L = synth.dominant_lower(n, (18, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (18, 0, 1))
+    nbytes = rs.mixed_workspace_bytes("L", n, nrhs, 2)
+    assert nbytes >= n * n * 6 + n * nrhs * 20
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+    st = rs.trsm_mixed(dL, dB, inner=2, work=work)
+    torch.cuda.synchronize()
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, dB.cpu().numpy()) <= 1e-12
+    small = torch.empty(nbytes - 1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rs.RedseaError) as e:
+        rs.trsm_mixed(dL, rs.fortran_tensor(B), inner=2, work=small)
+    assert e.value.code == -16
+
+
+def test_precision_option_of_trsm_routes_to_refinement():
+    n, nrhs = 600, 50
+    L = synth.kappa_lower(n, 0.05, (19, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (19, 0, 1))
+    for prec in ("fp32_ir", "bf16_ir"):
+        dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+        rs.trsm(dL, dB, precision=prec)
+        torch.cuda.synchronize()
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, dB.cpu().numpy()) <= 1e-12
+
+
+def test_larger_sampled():
+    n, nrhs = 8192, 512
+    L = synth.kappa_lower(n, 0.03, (20, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (20, 0, 1))
+    for inner in (1, 2):
+        dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+        st = rs.trsm_mixed(dL, dB, inner=inner)
+        torch.cuda.synchronize()
+        cols = [0, 255, 511]
+        Xs = dB[:, cols].cpu().numpy()
+        eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, cols]), Xs)
+        _say("n=8192 inner", inner, "iters", st.iterations, "fell_back", st.fell_back, "eta", eta)
+        assert eta <= 1e-12
