@@ -77,11 +77,16 @@ typedef enum {
 
 /* Solver options; a NULL pointer means every field AUTO.  nb is the leaf
  * (diagonal block) order; 0 = AUTO, otherwise one of 16, 32, 64, 128, 256,
- * 512. */
+ * 512.  kappa is the caller's estimate of the condition number of op(A)
+ * (0 = unknown: the library then uses max|a_ii| / min|a_ii|); it only
+ * informs the automatic choice, never the arithmetic.  When variant, nb and
+ * precision are all AUTO the learned picker chooses them (see
+ * redsea_pick). */
 typedef struct {
     int variant;   /* redsea_variant   */
     int nb;        /* leaf size or 0   */
     int precision; /* redsea_precision */
+    double kappa;  /* condition estimate or 0 */
 } redsea_opts;
 
 enum {
@@ -234,6 +239,69 @@ enum {
 };
 void redsea_trace_begin(void);
 int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds);
+
+/*
+ * Candidate schedules of the picker: index = 15*(variant-1) + 3*nb_index +
+ * precision_index with variant in {recursive, iterative, blocked}, nb in
+ * {32, 64, 128, 256, 512} and precision in {native, FP32+IR, BF16+IR}: 45
+ * candidates.  redsea_candidate decodes an index (returns -1 if out of
+ * range).  HOST call.
+ */
+enum { REDSEA_CANDIDATES = 45 };
+int redsea_candidate(int index, int* variant, int* nb, int* precision);
+
+/*
+ * Exhaustive autotuner for one shape (spec learned part: the timings it
+ * produces train the picker, and the picker falls back to it).  Generates a
+ * left/lower/no-transpose system of order n with nrhs right-hand sides on the
+ * device (strict lower part uniform in (-1, 1) from a counter-based hash of
+ * (seed, i, j); diagonal 1 + sum|row| when c <= 0, else the constant
+ * c * (1 + max row sum), which sets the condition number), then times each
+ * listed candidate: `reps` runs after one warm-up, B restored between runs,
+ * median in milliseconds written to ms[i] (-1 for a candidate that does not
+ * apply, e.g. refinement for FP32 data).  cand: HOST array of ncand indices.
+ * Synchronous; allocates and frees its own device buffers.  Argument
+ * numbers: dtype 1, n 2, nrhs 3, c 4, seed 5, reps 6, cand 7, ncand 8, ms 9,
+ * stream 10.
+ */
+int redsea_tune_shape(int dtype, int64_t n, int64_t nrhs, double c, uint64_t seed, int reps,
+                      const int* cand, int ncand, double* ms, void* stream);
+
+/*
+ * Learned picker: a 3-layer FP32 MLP (5 -> 64 -> 64 -> 45, ReLU) that maps
+ * (log2 n, log2 nrhs, dtype, log10 kappa, log2 batch), normalised, to the
+ * predicted log time of each candidate.  Parameters are packed as W1 (64x5,
+ * row-major), b1, W2 (64x64), b2, W3 (45x64), b3: redsea_mlp_param_count()
+ * floats.  All pointers below are DEVICE pointers; X is nb x 5 row-major
+ * (already normalised), Y, T and mask are nb x 45.  The kernels are
+ * deterministic (no atomics).
+ *   forward: Y = MLP(X).
+ *   grad   : gradient of the masked mean squared error
+ *            sum(mask (Y - T)^2) / sum(mask) into grad (packed like params)
+ *            and the loss into loss[0].
+ *   adam   : one Adam step (bias-corrected, step >= 1) on params with moment
+ *            buffers m, v (packed like params, zero-initialised by the caller).
+ * Argument numbers follow the declaration order.
+ */
+int redsea_mlp_param_count(void);
+int redsea_mlp_forward(const float* params, const float* X, int64_t nb, float* Y, void* stream);
+int redsea_mlp_grad(const float* params, const float* X, const float* T, const float* mask,
+                    int64_t nb, float* grad, float* loss, void* stream);
+int redsea_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream);
+
+/*
+ * Picker decision for a solve (HOST call, no device work): the candidate
+ * index the library would use for a left solve of order n with nrhs
+ * right-hand sides, data type dtype and condition estimate kappa (<= 0:
+ * unknown), or -1 when no trained weights are loaded.  *confident is set to
+ * 1 when the prediction is inside the training range and the best two
+ * predictions differ by more than 5 %.  Weights come from the file named by
+ * REDSEA_MLP_WEIGHTS, else picker_weights.txt next to the library;
+ * redsea_mlp_load(path) loads a file explicitly (returns 0 or -1).
+ */
+int redsea_pick(int dtype, int64_t n, int64_t nrhs, double kappa, int* confident);
+int redsea_mlp_load(const char* path);
 
 /* Library version as "major.minor.patch". */
 const char* redsea_version(void);

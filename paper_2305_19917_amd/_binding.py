@@ -29,6 +29,14 @@ EXPORTS = (
     "redsea_batched_plan_destroy",
     "redsea_trace_begin",
     "redsea_trace_end",
+    "redsea_candidate",
+    "redsea_tune_shape",
+    "redsea_mlp_param_count",
+    "redsea_mlp_forward",
+    "redsea_mlp_grad",
+    "redsea_mlp_adam",
+    "redsea_pick",
+    "redsea_mlp_load",
 )
 KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group")
 
@@ -49,7 +57,8 @@ class RedseaError(RuntimeError):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int), ("nb", ctypes.c_int), ("precision", ctypes.c_int)]
+    _fields_ = [("variant", ctypes.c_int), ("nb", ctypes.c_int), ("precision", ctypes.c_int),
+                ("kappa", ctypes.c_double)]
 
 
 class MixedStats(ctypes.Structure):
@@ -98,6 +107,24 @@ def lib() -> ctypes.CDLL:
     L.redsea_batched_plan_run.argtypes = [ptr, ptr, ptr]
     L.redsea_batched_plan_destroy.restype = None
     L.redsea_batched_plan_destroy.argtypes = [ptr]
+    L.redsea_candidate.restype = cint
+    L.redsea_candidate.argtypes = [cint, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint)]
+    L.redsea_tune_shape.restype = cint
+    L.redsea_tune_shape.argtypes = [cint, i64, i64, dbl, ctypes.c_uint64, cint, ctypes.POINTER(cint),
+                                    cint, ctypes.POINTER(dbl), ptr]
+    L.redsea_mlp_param_count.restype = cint
+    L.redsea_mlp_param_count.argtypes = []
+    L.redsea_mlp_forward.restype = cint
+    L.redsea_mlp_forward.argtypes = [ptr, ptr, i64, ptr, ptr]
+    L.redsea_mlp_grad.restype = cint
+    L.redsea_mlp_grad.argtypes = [ptr, ptr, ptr, ptr, i64, ptr, ptr, ptr]
+    L.redsea_mlp_adam.restype = cint
+    L.redsea_mlp_adam.argtypes = [ptr, ptr, ptr, ptr, i64, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, ptr]
+    L.redsea_pick.restype = cint
+    L.redsea_pick.argtypes = [cint, i64, i64, dbl, ctypes.POINTER(cint)]
+    L.redsea_mlp_load.restype = cint
+    L.redsea_mlp_load.argtypes = [ctypes.c_char_p]
     L.redsea_trace_begin.restype = None
     L.redsea_trace_begin.argtypes = []
     L.redsea_trace_end.restype = cint

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -15,6 +16,7 @@
 #include "exec.h"
 #include "kernels.h"
 #include "mixed.h"
+#include "picker.h"
 #include "plan.h"
 
 namespace redsea {
@@ -374,6 +376,41 @@ int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
     return rc;
 }
 
+// Exhaustive tuning of one shape on generated data (only when the
+// REDSEA_TUNE environment variable is 1), cached per process.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int64_t, int>, int> g_tuned;
+}  // namespace
+
+int tuned_candidate(int dtype, int64_t k, int64_t nrhs, double kappa, hipStream_t s) {
+    const char* e = std::getenv("REDSEA_TUNE");
+    if (!e || std::atoi(e) != 1) return -1;
+    const int kclass = (int)std::lround(std::log10(kappa > 1.0 ? kappa : 1.0));
+    auto key = std::make_tuple(dtype, k, nrhs, kclass);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
+    std::vector<int> cand;
+    for (int c = 0; c < REDSEA_CANDIDATES; ++c)
+        if (dtype == REDSEA_F64 || c % 3 == 0) cand.push_back(c);
+    std::vector<double> ms(cand.size(), -1.0);
+    // the generator's constant diagonal reaches roughly this condition number
+    const double cdiag = kappa >= 1e5 ? 0.004 : kappa >= 1e3 ? 0.012 : kappa >= 50 ? 0.1 : 0.0;
+    if (redsea_tune_shape(dtype, k, nrhs, cdiag, 12345, 2, cand.data(), (int)cand.size(), ms.data(),
+                          s) != REDSEA_OK)
+        return -1;
+    int best = -1;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (ms[i] > 0 && (best < 0 || ms[i] < ms[best])) best = (int)i;
+    const int pick = best < 0 ? -1 : cand[best];
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[key] = pick;
+    return pick;
+}
+
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a) {
     if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
@@ -451,6 +488,25 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
     if (precision < 0 || precision > 3) return -13;
     if (m == 0 || n == 0) return REDSEA_OK;
     hipStream_t s = (hipStream_t)stream;
+    redsea_opts chosen = opts ? *opts : redsea_opts{0, 0, 0, 0.0};
+    if (variant == 0 && nb == 0 && precision == 0 && alpha != 0.0) {
+        // learned picker (falls back to the exhaustive tuner when asked to and
+        // not confident); a condition estimate, when not given, is taken as
+        // that of a diagonally dominant matrix of this order
+        const int64_t k = side == REDSEA_LEFT ? m : n, nrhs = side == REDSEA_LEFT ? n : m;
+        const double kap = chosen.kappa > 0.0 ? chosen.kappa : 4.5 * (double)k;
+        int confident = 0;
+        int cand = pick_candidate(dtype, k, nrhs, kap, &confident);
+        if (!confident) {
+            int tuned = tuned_candidate(dtype, k, nrhs, kap, s);
+            if (tuned >= 0) cand = tuned;
+        }
+        if (cand >= 0) decode_candidate(cand, &variant, &nb, &precision);
+        chosen.variant = variant;
+        chosen.nb = nb;
+        chosen.precision = precision;
+        opts = &chosen;
+    }
     if (alpha != 0.0 && (precision == REDSEA_PREC_FP32_IR || precision == REDSEA_PREC_BF16_IR)) {
         if (dtype != REDSEA_F64) return REDSEA_ERR_UNSUPPORTED;
         const int inner = precision == REDSEA_PREC_FP32_IR ? 1 : 2;

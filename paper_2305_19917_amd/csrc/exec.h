@@ -42,6 +42,7 @@ int workspace(int slot, size_t bytes, void** out);
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
 int pick_nb(int requested, int64_t k);
+int tuned_candidate(int dtype, int64_t k, int64_t nrhs, double kappa, hipStream_t s);
 int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
                 const double* A, int64_t lda, double* B, int64_t ldb, int inner, double tol,
                 int max_iter, void* work, size_t work_bytes, redsea_mixed_stats* stats,

@@ -1,0 +1,304 @@
+// Exhaustive autotuner, candidate encoding, and the learned picker's host
+// inference and weight file.  The paper picks its refinement level with an
+// analytic cost model and a stop rule (Sec. V-A); here measured timings train
+// a small network that predicts the time of every candidate schedule.
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/redsea.h"
+#include "exec.h"
+#include "picker.h"
+
+namespace redsea {
+
+namespace {
+
+const int kNbs[5] = {32, 64, 128, 256, 512};
+
+struct Net {
+    bool loaded = false;
+    float mu[5], sd[5];
+    float lo[2], hi[2];  // training range of log2 n and log2 nrhs
+    std::vector<float> P;
+};
+
+std::mutex g_net_mu;
+Net g_net;
+bool g_tried = false;
+
+bool load_file(const char* path, Net& net) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string magic;
+    int ver = 0, in = 0, h1 = 0, h2 = 0, out = 0;
+    f >> magic >> ver >> in >> h1 >> h2 >> out;
+    const MlpShape S;
+    if (!f || magic != "redsea-mlp" || ver != 1 || in != S.in || h1 != S.h1 || h2 != S.h2 ||
+        out != S.out)
+        return false;
+    for (int i = 0; i < 5; ++i) f >> net.mu[i];
+    for (int i = 0; i < 5; ++i) f >> net.sd[i];
+    f >> net.lo[0] >> net.hi[0] >> net.lo[1] >> net.hi[1];
+    net.P.resize(S.count());
+    for (int i = 0; i < S.count(); ++i) f >> net.P[i];
+    if (!f) return false;
+    net.loaded = true;
+    return true;
+}
+
+void ensure_loaded() {
+    if (g_tried) return;
+    g_tried = true;
+    const char* env = std::getenv("REDSEA_MLP_WEIGHTS");
+    if (env && load_file(env, g_net)) return;
+    Dl_info info;
+    if (dladdr((void*)&ensure_loaded, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        size_t slash = p.find_last_of('/');
+        std::string dir = slash == std::string::npos ? "." : p.substr(0, slash);
+        load_file((dir + "/picker_weights.txt").c_str(), g_net);
+    }
+}
+
+// y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 on the host (double accumulation)
+void host_forward(const Net& net, const float x[5], double y[45]) {
+    const MlpShape S;
+    const float* P = net.P.data();
+    double h1[64], h2[64];
+    for (int o = 0; o < S.h1; ++o) {
+        double a = P[S.b1() + o];
+        for (int i = 0; i < S.in; ++i) a += (double)P[S.w1() + o * S.in + i] * x[i];
+        h1[o] = a > 0 ? a : 0;
+    }
+    for (int o = 0; o < S.h2; ++o) {
+        double a = P[S.b2() + o];
+        for (int i = 0; i < S.h1; ++i) a += (double)P[S.w2() + o * S.h1 + i] * h1[i];
+        h2[o] = a > 0 ? a : 0;
+    }
+    for (int o = 0; o < S.out; ++o) {
+        double a = P[S.b3() + o];
+        for (int i = 0; i < S.h2; ++i) a += (double)P[S.w3() + o * S.h2 + i] * h2[i];
+        y[o] = a;
+    }
+}
+
+}  // namespace
+
+void decode_candidate(int idx, int* variant, int* nb, int* precision) {
+    *variant = idx / 15 + 1;
+    *nb = kNbs[(idx % 15) / 3];
+    *precision = idx % 3 + 1;
+}
+
+int pick_candidate(int dtype, int64_t n, int64_t nrhs, double kappa, int* confident) {
+    std::lock_guard<std::mutex> lock(g_net_mu);
+    ensure_loaded();
+    if (confident) *confident = 0;
+    if (!g_net.loaded) return -1;
+    const double ln = std::log2((double)std::max<int64_t>(n, 1));
+    const double lr = std::log2((double)std::max<int64_t>(nrhs, 1));
+    const double lk = std::log10(kappa > 1.0 ? kappa : 1.0);
+    const double raw[5] = {ln, lr, (double)dtype, lk, 0.0};
+    float x[5];
+    for (int i = 0; i < 5; ++i) x[i] = (float)((raw[i] - g_net.mu[i]) / g_net.sd[i]);
+    double y[45];
+    host_forward(g_net, x, y);
+    int best = -1, second = -1;
+    for (int c = 0; c < 45; ++c) {
+        if (dtype != 0 && c % 3 != 0) continue;  // refinement applies to FP64 data only
+        if (best < 0 || y[c] < y[best]) {
+            second = best;
+            best = c;
+        } else if (second < 0 || y[c] < y[second]) {
+            second = c;
+        }
+    }
+    if (confident) {
+        const bool in_range = ln >= g_net.lo[0] && ln <= g_net.hi[0] && lr >= g_net.lo[1] &&
+                              lr <= g_net.hi[1];
+        const bool separated = second < 0 || (y[second] - y[best]) > std::log(1.05);
+        *confident = in_range && separated ? 1 : 0;
+    }
+    return best;
+}
+
+}  // namespace redsea
+
+using namespace redsea;
+
+extern "C" {
+
+int redsea_candidate(int index, int* variant, int* nb, int* precision) {
+    if (index < 0 || index >= REDSEA_CANDIDATES) return -1;
+    int v, b, p;
+    decode_candidate(index, &v, &b, &p);
+    if (variant) *variant = v;
+    if (nb) *nb = b;
+    if (precision) *precision = p;
+    return 0;
+}
+
+int redsea_mlp_load(const char* path) {
+    if (!path) return -1;
+    Net net;
+    if (!load_file(path, net)) return -1;
+    std::lock_guard<std::mutex> lock(g_net_mu);
+    g_net = net;
+    g_tried = true;
+    return 0;
+}
+
+int redsea_pick(int dtype, int64_t n, int64_t nrhs, double kappa, int* confident) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    return pick_candidate(dtype, n, nrhs, kappa, confident);
+}
+
+int redsea_mlp_param_count(void) { return MlpShape().count(); }
+
+int redsea_mlp_forward(const float* params, const float* X, int64_t nb, float* Y, void* stream) {
+    if (!params) return -1;
+    if (nb < 0) return -3;
+    if (nb == 0) return REDSEA_OK;
+    if (!X) return -2;
+    if (!Y) return -4;
+    hipStream_t s = (hipStream_t)stream;
+    float* tmp = nullptr;
+    int rc = workspace(3, (size_t)nb * (64 + 64) * sizeof(float), (void**)&tmp);
+    if (rc) return rc;
+    return mlp_forward_dev(params, X, nb, tmp, tmp + nb * 64, Y, s) == hipSuccess ? REDSEA_OK
+                                                                                 : REDSEA_ERR_HIP;
+}
+
+int redsea_mlp_grad(const float* params, const float* X, const float* T, const float* mask,
+                    int64_t nb, float* grad, float* loss, void* stream) {
+    if (!params) return -1;
+    if (nb <= 0) return -5;
+    if (!X) return -2;
+    if (!T) return -3;
+    if (!mask) return -4;
+    if (!grad) return -6;
+    if (!loss) return -7;
+    float* tmp = nullptr;
+    int rc = workspace(4, ((size_t)nb * (64 + 64 + 45 + 45 + 64 + 64) + 1) * sizeof(float),
+                       (void**)&tmp);
+    if (rc) return rc;
+    return mlp_grad_dev(params, X, T, mask, nb, grad, loss, tmp, (hipStream_t)stream) ==
+                   hipSuccess
+               ? REDSEA_OK
+               : REDSEA_ERR_HIP;
+}
+
+int redsea_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t step, float lr,
+                    float beta1, float beta2, float eps, void* stream) {
+    if (!params) return -1;
+    if (!grad) return -2;
+    if (!m) return -3;
+    if (!v) return -4;
+    if (step < 1) return -5;
+    return mlp_adam_dev(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream) ==
+                   hipSuccess
+               ? REDSEA_OK
+               : REDSEA_ERR_HIP;
+}
+
+int redsea_tune_shape(int dtype, int64_t n, int64_t nrhs, double c, uint64_t seed, int reps,
+                      const int* cand, int ncand, double* ms, void* stream) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (n <= 0) return -2;
+    if (nrhs <= 0) return -3;
+    if (reps < 1) return -6;
+    if (ncand < 0) return -8;
+    if (ncand > 0 && !cand) return -7;
+    if (ncand > 0 && !ms) return -9;
+    for (int i = 0; i < ncand; ++i)
+        if (cand[i] < 0 || cand[i] >= REDSEA_CANDIDATES) return -7;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = dtype == REDSEA_F64 ? 8 : 4;
+    double *A64 = nullptr, *B64 = nullptr, *rows = nullptr;
+    void *A = nullptr, *B0 = nullptr, *B = nullptr;
+    auto cleanup = [&]() {
+        if (A64) (void)hipFree(A64);
+        if (B64) (void)hipFree(B64);
+        if (rows) (void)hipFree(rows);
+        if (dtype != REDSEA_F64 && A) (void)hipFree(A);
+        if (dtype != REDSEA_F64 && B0) (void)hipFree(B0);
+        if (B) (void)hipFree(B);
+    };
+    const size_t an = (size_t)n * n, bn = (size_t)n * nrhs;
+    bool ok = hipMalloc(&A64, an * 8) == hipSuccess && hipMalloc(&B64, bn * 8) == hipSuccess &&
+              hipMalloc(&rows, (size_t)n * 8) == hipSuccess && hipMalloc(&B, bn * es) == hipSuccess;
+    if (ok && dtype != REDSEA_F64)
+        ok = hipMalloc(&A, an * 4) == hipSuccess && hipMalloc(&B0, bn * 4) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        cleanup();
+        return REDSEA_ERR_ALLOC;
+    }
+    if (gen_system_dev(A64, n, n, c, seed, rows, s) != hipSuccess ||
+        gen_rhs_dev(B64, n, n, nrhs, seed + 1, s) != hipSuccess) {
+        cleanup();
+        return REDSEA_ERR_HIP;
+    }
+    if (dtype == REDSEA_F64) {
+        A = A64;
+        B0 = B64;
+    } else if (narrow_dev(A64, (int64_t)an, (float*)A, s) != hipSuccess ||
+               narrow_dev(B64, (int64_t)bn, (float*)B0, s) != hipSuccess) {
+        cleanup();
+        return REDSEA_ERR_HIP;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return REDSEA_ERR_HIP;
+    }
+    int rc = REDSEA_OK;
+    for (int ci = 0; ci < ncand && rc == REDSEA_OK; ++ci) {
+        int v, nb, p;
+        decode_candidate(cand[ci], &v, &nb, &p);
+        if (dtype != REDSEA_F64 && p != REDSEA_PREC_NATIVE) {
+            ms[ci] = -1.0;
+            continue;
+        }
+        redsea_opts o;
+        o.variant = v;
+        o.nb = nb;
+        o.precision = p;
+        o.kappa = 0.0;
+        std::vector<float> t;
+        for (int r = 0; r <= reps && rc == REDSEA_OK; ++r) {
+            if (hipMemcpyAsync(B, B0, bn * es, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                rc = REDSEA_ERR_HIP;
+                break;
+            }
+            (void)hipEventRecord(e0, s);
+            rc = redsea_trsm(dtype, REDSEA_LEFT, REDSEA_LOWER, REDSEA_NOTRANS, REDSEA_NONUNIT, n,
+                             nrhs, 1.0, A, n, B, n, &o, s);
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) rc = REDSEA_ERR_HIP;
+            float el = 0.f;
+            (void)hipEventElapsedTime(&el, e0, e1);
+            if (r > 0) t.push_back(el);  // the first run warms up
+        }
+        if (rc == REDSEA_OK) {
+            std::sort(t.begin(), t.end());
+            ms[ci] = t[t.size() / 2];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    return rc;
+}
+
+}  // extern "C"
