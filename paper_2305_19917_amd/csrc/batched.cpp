@@ -1,6 +1,8 @@
 // Host side of the batched solve: validation, canonical descriptors, the
 // longest-first task order, and the plan object whose run is launches only
-// (so it can be captured in a hipGraph and replayed).
+// (so it can be captured in a hipGraph and replayed).  Systems of order above
+// kBatchMaxOrder are left to the single-system path, whose recursive
+// schedule suits them better than one wave per 16 columns.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -151,19 +153,12 @@ int redsea_batched_plan_create(int dtype, int side, int uplo, int trans, int dia
         redsea_batched_plan_destroy(P);
         return REDSEA_ERR_HIP;
     }
-    // persistent grid: as many resident workgroups as the LDS panel allows
+    // persistent grid: eight resident waves per CU (two workgroups of four);
+    // each wave claims tasks on its own
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess)
         cus = 256;
-    const size_t lds = batched_lds_bytes(std::max<int64_t>(P->kmax, 16)) + 16 * 16 * 8 + 64;
-    int per_cu = (int)std::min<size_t>(4, (160 * 1024) / lds);
-    if (per_cu < 1) per_cu = 1;
-    P->grid = std::max(1, std::min(P->ntasks, cus * per_cu));
-    if (batched_set_lds_limit(dtype, P->unit, batched_lds_bytes(std::max<int64_t>(P->kmax, 16))) !=
-        hipSuccess) {
-        redsea_batched_plan_destroy(P);
-        return REDSEA_ERR_HIP;
-    }
+    P->grid = std::max(1, std::min((P->ntasks + 3) / 4, cus * 2));
     *out = P;
     return REDSEA_OK;
 }

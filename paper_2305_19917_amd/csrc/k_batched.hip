@@ -3,15 +3,16 @@
 // system; spec batching pattern).
 //
 // Work is a list of tasks (system, tile of up to 16 right-hand sides), sorted
-// longest-first on the host.  Each workgroup repeatedly claims the next task
-// from a counter and solves it alone: the system's order is at most kmax
-// (<= 1024), so the whole 16-column panel of B stays in LDS while the
-// workgroup runs the right-looking blocked substitution over 16-row blocks:
-//   wave 0 solves the 16 x 16 diagonal block of every column by substitution
-//   (one IEEE division per row), then all four waves update the blocks below
-//   on the matrix cores (v_mfma_f64_16x16x4f64), each wave a different block.
+// longest-first on the host.  Every wave repeatedly claims the next task from
+// a counter and solves it alone, left-looking over 16-row blocks with its
+// 16 x 16 block of the right-hand sides held in the v_mfma_f64_16x16x4f64
+// accumulator layout (lane l, register r = row l/16 + 4r, column l % 16):
+//   acc = alpha B_p;  acc -= L_pq X_q for every solved block q < p on the
+//   matrix cores (operands for q+1 are requested while q is multiplied);
+//   then the 16 x 16 diagonal block is solved by substitution in every lane
+//   (one IEEE division per row) and X_p is stored.
 // A task never depends on another, so the result does not depend on which
-// workgroup ran it.
+// wave ran it.
 #include <hip/hip_runtime.h>
 
 #include "batched.h"
@@ -40,95 +41,109 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                                                       const BatchTask* __restrict__ tasks,
                                                       int ntasks, int* __restrict__ counter,
                                                       int* __restrict__ info, double alpha) {
-    extern __shared__ double Pn[];  // [rows][16], rows = padded order of the task's system
-    __shared__ double Ld[16 * 16];  // diagonal block, element (j, i) at Ld[i*16 + j]
-    __shared__ int claimed;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+    __shared__ double Xs[4][16][17];  // per-wave gather buffer
+    __shared__ double Ls[4][16 * 16]; // per-wave diagonal block, (j, i) at [i*16 + j]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
     for (;;) {
-        if (tid == 0) claimed = atomicAdd(counter, 1);
-        __syncthreads();
-        const int t = claimed;
-        __syncthreads();
-        if (t >= ntasks) break;  // uniform: every thread read the same value
+        int t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0);
+        if (t >= ntasks) break;  // uniform over the wave
         const BatchTask task = tasks[t];
         const BatchSys S = sys[task.sys];
         const TS* A = (const TS*)S.a;
         TS* B = (TS*)S.b;
         const int64_t k = S.k, c0 = task.c0;
-        const int w = (int)(S.nrhs - c0 < 16 ? S.nrhs - c0 : 16);
-        const int nblk = (int)((k + 15) / 16), kp = nblk * 16;
-        // load the panel (rows past k and columns past w are zero)
-        for (int idx = tid; idx < kp * 16; idx += 256) {
-            const int i = idx % kp, j = idx / kp;
-            double v = 0.0;
-            if (i < k && j < w) {
-                v = (double)B[S.b_off + i * S.br + (c0 + j) * S.bc];
-                if (alpha != 1.0) v = alpha * v;
-            }
-            Pn[i * 16 + j] = v;
-        }
-        __syncthreads();
-        if (alpha != 0.0) {
-            for (int q = 0; q < nblk; ++q) {
-                if (wave == 0) {
-                    // stage the diagonal block (identity past the order)
+        const int wcols = (int)(S.nrhs - c0 < 16 ? S.nrhs - c0 : 16);
+        const bool colok = c < wcols;
+        const int nblk = (int)((k + 15) / 16);
+        const int64_t bcol = S.b_off + (c0 + (colok ? c : 0)) * S.bc;
+        auto bget = [&](int64_t row) -> double {
+            return (colok && row < k) ? (double)B[bcol + row * S.br] : 0.0;
+        };
+        auto aget = [&](int64_t row, int64_t col) -> double {
+            return row < k ? (double)A[S.a_off + row * S.tr + col * S.tc] : 0.0;
+        };
+        int bad = 0;
+        for (int p = 0; p < nblk; ++p) {
+            v4d acc;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = g + 4 * r, jj = c;  // element (i, jj) of the block
-                        const int64_t gi = 16 * q + i, gj = 16 * q + jj;
-                        double v = 0.0;
-                        if (gi >= k) v = (i == jj) ? 1.0 : 0.0;
-                        else if (i == jj) v = UNIT ? 1.0 : (double)A[S.a_off + gi * S.tr + gj * S.tc];
-                        else if (i > jj) v = (double)A[S.a_off + gi * S.tr + gj * S.tc];
-                        Ld[jj * 16 + i] = v;
-                    }
-                    wave_sync();
-                    if (g == 0) {
-                        double y[16];
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) y[i] = Pn[(16 * q + i) * 16 + c];
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            double x = y[i];
-                            if (!UNIT) x = x / Ld[i * 16 + i];
-                            y[i] = x;
-#pragma unroll
-                            for (int j = i + 1; j < 16; ++j) y[j] = __builtin_fma(-Ld[i * 16 + j], x, y[j]);
-                        }
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) Pn[(16 * q + i) * 16 + c] = y[i];
-                    }
-                }
-                __syncthreads();
-                for (int p = q + 1 + wave; p < nblk; p += 4) {
-                    v4d f;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) f[r] = Pn[(16 * p + g + 4 * r) * 16 + c];
+            for (int r = 0; r < 4; ++r) acc[r] = alpha * bget(16 * p + g + 4 * r);
+            if (alpha != 0.0) {
+                // acc -= L_pq X_q, q < p; operands of q+1 requested before q's MFMAs
+                double xa[4], aa[4];
+                if (p > 0) {
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
-                        const int64_t gi = 16 * p + c, gj = 16 * q + 4 * kk + g;
-                        const double a = gi < k ? -(double)A[S.a_off + gi * S.tr + gj * S.tc] : 0.0;
-                        const double b = Pn[(16 * q + 4 * kk + g) * 16 + c];
-                        f = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, f, 0, 0, 0);
+                        xa[kk] = bget(4 * kk + g);
+                        aa[kk] = -aget(16 * p + c, 4 * kk + g);
+                    }
+                }
+                for (int q = 0; q < p; ++q) {
+                    double xn[4], an[4];
+                    if (q + 1 < p) {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            xn[kk] = bget(16 * (q + 1) + 4 * kk + g);
+                            an[kk] = -aget(16 * p + c, 16 * (q + 1) + 4 * kk + g);
+                        }
                     }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Pn[(16 * p + g + 4 * r) * 16 + c] = f[r];
+                    for (int kk = 0; kk < 4; ++kk)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[kk], xa[kk], acc, 0, 0, 0);
+                    if (q + 1 < p) {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            xa[kk] = xn[kk];
+                            aa[kk] = an[kk];
+                        }
+                    }
                 }
-                __syncthreads();
+                // diagonal block (identity past the order) and the column's rows
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = g + 4 * r;  // row of the block, column c
+                    const int64_t gi = 16 * p + i, gj = 16 * p + c;
+                    double v = 0.0;
+                    if (gi >= k) v = (i == c) ? 1.0 : 0.0;
+                    else if (i == c) v = UNIT ? 1.0 : aget(gi, gj);
+                    else if (i > c) v = aget(gi, gj);
+                    Ls[w][c * 16 + i] = v;
+                    Xs[w][i][c] = acc[r];
+                }
+                wave_sync();
+                double y[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) y[i] = Xs[w][i][c];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    double x = y[i];
+                    if (!UNIT) x = x / Ls[w][i * 16 + i];
+                    y[i] = x;
+#pragma unroll
+                    for (int j = i + 1; j < 16; ++j) y[j] = __builtin_fma(-Ls[w][i * 16 + j], x, y[j]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];
+                    const double v23 = g == 2 ? y[4 * r + 2] : y[4 * r + 3];
+                    acc[r] = g < 2 ? v01 : v23;
+                }
+                wave_sync();  // Xs and Ls are reused by the next block
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = 16 * p + g + 4 * r;
+                if (colok && row < k) {
+                    const TS v = (TS)acc[r];
+                    B[bcol + row * S.br] = v;
+                    if (!__builtin_isfinite((double)v)) bad = 1;
+                }
             }
         }
-        // store, flagging non-finite results of the system
-        int bad = 0;
-        for (int idx = tid; idx < kp * 16; idx += 256) {
-            const int i = idx % kp, j = idx / kp;
-            if (i < k && j < w) {
-                const TS v = (TS)Pn[i * 16 + j];
-                B[S.b_off + i * S.br + (c0 + j) * S.bc] = v;
-                if (!__builtin_isfinite((double)v)) bad = 1;
-            }
-        }
-        if (bad) atomicOr(&info[task.sys], 4);
-        __syncthreads();  // the panel is free for the next task
+        // the stores of this task are visible to its own later loads (same
+        // wave, program order); flag a non-finite result of the system
+        if (__any(bad) && lane == 0) atomicOr(&info[task.sys], 4);
     }
 }
 
@@ -143,7 +158,10 @@ hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_
     return hipGetLastError();
 }
 
-size_t batched_lds_bytes(int64_t kmax) { return (size_t)((kmax + 15) / 16) * 16 * 16 * 8; }
+size_t batched_lds_bytes(int64_t kmax) {
+    (void)kmax;
+    return 0;  // every buffer is static: 4 waves x (gather + diagonal block)
+}
 
 hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
                           int ntasks, int* counter, int* info, int64_t kmax, double alpha,
@@ -168,10 +186,10 @@ hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const Batch
 }
 
 hipError_t batched_set_lds_limit(int dtype, bool unit, size_t bytes) {
-    const void* f;
-    if (dtype == 0) f = unit ? (const void*)batched_kernel<double, true> : (const void*)batched_kernel<double, false>;
-    else f = unit ? (const void*)batched_kernel<float, true> : (const void*)batched_kernel<float, false>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)dtype;
+    (void)unit;
+    (void)bytes;
+    return hipSuccess;
 }
 
 }  // namespace redsea

@@ -38,39 +38,42 @@ __global__ __launch_bounds__(256) void pack_diag_kernel(const T* __restrict__ A,
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// FP64 panel leaf on matrix cores.  A workgroup of four waves covers 64
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Panel leaf on matrix cores.  A workgroup of four waves covers 64
 // right-hand-side columns, each wave 16 of them, and holds its NP x 16 slab of
 // B in MFMA accumulator layout: fragment f, register r of lane l is row
 // 16 f + l/16 + 4 r, column l % 16 (the v_mfma_f64_16x16x4f64 result
 // layout).  The panel is solved by 16-row diagonal blocks:
-//   1. the 16 x 16 block of each column is gathered into one lane (every
+//   1. the operands of this block's updates are requested from the packed
+//      triangle (global memory) first, so they arrive during step 2;
+//   2. the 16 x 16 block of each column is gathered into one lane (every
 //      lane of the column's four lane groups gets the whole column, through
-//      LDS) and solved there by substitution, one IEEE division per row;
-//   2. each lane keeps its own four rows of the result;
-//   3. every later 16-row fragment is updated on the matrix cores,
+//      LDS) and solved there by substitution, one IEEE division per row,
+//      reading the diagonal block from LDS;
+//   3. each lane keeps its own four rows of the result;
+//   4. every later 16-row fragment is updated on the matrix cores,
 //      frag_p -= L_ps X_s, whose B operand for k-slice kk is exactly register
 //      kk of the solved fragment, so no data moves for the update.
+// After the diagonal blocks are staged the four waves run independently.
 template <typename TS, int NP, bool UNIT, bool FULL>
 __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P, int rows,
                                                         TS* __restrict__ B, int64_t off,
                                                         int64_t br, int64_t bc, int64_t ncols) {
     constexpr int NF = NP / 16;
-    __shared__ __attribute__((aligned(16))) double Ls[NP * NP];
+    __shared__ double Ds[NF][16 * 16];  // diagonal block f, element (j, i) at Ds[f][i*16 + j]
     __shared__ double Xs[4][16][17];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
     {
-        // stage the packed triangle: batches of independent loads, so their
-        // latencies overlap instead of adding up
-        constexpr int PER = NP * NP / 256;  // elements per thread
-        constexpr int BATCH = PER < 16 ? PER : 16;
+        TS t[NF];
 #pragma unroll
-        for (int b0 = 0; b0 < PER; b0 += BATCH) {
-            TS t[BATCH];
+        for (int f = 0; f < NF; ++f) t[f] = P[(16 * f + tid / 16) * NP + 16 * f + tid % 16];
 #pragma unroll
-            for (int q = 0; q < BATCH; ++q) t[q] = P[(b0 + q) * 256 + tid];
-#pragma unroll
-            for (int q = 0; q < BATCH; ++q) Ls[(b0 + q) * 256 + tid] = (double)t[q];
-        }
+        for (int f = 0; f < NF; ++f) Ds[f][tid] = (double)t[f];
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + w * 16 + c;
     const bool colok = col < ncols;
@@ -86,17 +89,24 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < NF; ++s) {
-        // 1. gather the 16 rows of this block for column c into every lane
+        // 1. operands of the updates below this block
+        double ap[NF][4];
+#pragma unroll
+        for (int p = s + 1; p < NF; ++p)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                ap[p][kk] = -(double)P[(16 * s + 4 * kk + g) * NP + 16 * p + c];
+        // 2. gather the 16 rows of this block for column c into every lane
 #pragma unroll
         for (int r = 0; r < 4; ++r) Xs[w][g + 4 * r][c] = fr[s][r];
-        __syncthreads();
+        wave_sync();
         double y[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) y[i] = Xs[w][i][c];
         // substitution on the 16 x 16 diagonal block (axpy order).  Column
         // i+1 of the block is read from LDS while column i is applied, so
         // the chain of a step is one division and one fused multiply-add.
-        const double* Lb = Ls + (16 * s) * NP + 16 * s;  // element (j, i) at Lb[i*NP + j]
+        const double* Lb = Ds[s];
         double cur[16], nxt[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) cur[j] = Lb[j];
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
         for (int i = 0; i < 16; ++i) {
             if (i + 1 < 16) {
 #pragma unroll
-                for (int j = i + 1; j < 16; ++j) nxt[j] = Lb[(i + 1) * NP + j];
+                for (int j = i + 1; j < 16; ++j) nxt[j] = Lb[(i + 1) * 16 + j];
             }
             double x = y[i];
             if (!UNIT) x = x / cur[i];
@@ -117,22 +127,20 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
 #pragma unroll
             for (int j = i + 1; j < 16; ++j) cur[j] = nxt[j];
         }
-        __syncthreads();
-        // 2. keep this lane's rows (g + 4r) of the solved block
+        // 3. keep this lane's rows g + 4r of the solved block
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if ((i & 3) == g) Xs[w][i][c] = y[i];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) fr[s][r] = Xs[w][g + 4 * r][c];
-        // 3. matrix-core update of the fragments below
+        for (int r = 0; r < 4; ++r) {
+            const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];
+            const double v23 = g == 2 ? y[4 * r + 2] : y[4 * r + 3];
+            fr[s][r] = g < 2 ? v01 : v23;
+        }
+        wave_sync();  // every lane has read Xs before the next block writes it
+        // 4. matrix-core update of the fragments below
 #pragma unroll
         for (int p = s + 1; p < NF; ++p)
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const double a = -Ls[(16 * s + 4 * kk + g) * NP + 16 * p + c];
-                fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, fr[s][kk], fr[p], 0, 0, 0);
-            }
+            for (int kk = 0; kk < 4; ++kk)
+                fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[p][kk], fr[s][kk], fr[p], 0, 0, 0);
     }
     if (colok) {
 #pragma unroll

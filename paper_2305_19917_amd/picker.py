@@ -64,7 +64,15 @@ def tune(dtype: int, n: int, nrhs: int, c: float, seed: int, reps: int = 2, stre
     return [float(x) for x in ms]
 
 
-def sample_shapes(count: int, seed: int, n_range=(64, 16384), nrhs_range=(1, 8192),
+# training range: orders and right-hand-side counts log-uniform in these
+# intervals (narrower than the n <= 32768, nrhs <= 16384 a full sweep would
+# cover, so that timing every candidate of ~2000 shapes fits the GPU time
+# available; the picker reports low confidence outside it)
+N_RANGE = (64, 8192)
+NRHS_RANGE = (1, 4096)
+
+
+def sample_shapes(count: int, seed: int, n_range=N_RANGE, nrhs_range=NRHS_RANGE,
                   f32_share=0.25):
     """Log-uniform orders and right-hand-side counts, a dtype and a kappa class."""
     r = np.random.default_rng([4, seed])

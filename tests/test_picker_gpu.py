@@ -80,20 +80,26 @@ def test_deterministic_gradient():
 
 
 def test_memorisation_drives_regret_to_zero():
-    """64 shapes with synthetic candidate times: training on them alone must
-    pick the fastest candidate of (almost) every one."""
+    """64 shapes with synthetic candidate times that vary smoothly with the
+    shape (each candidate's relative cost is a different smooth function of
+    log n and log nrhs): training on them alone must pick the fastest
+    candidate of (almost) every one."""
     r = np.random.default_rng(62)
     n = np.exp(r.uniform(np.log(64), np.log(16384), 64)).astype(int)
     k = np.exp(r.uniform(0, np.log(8192), 64)).astype(int)
     X = np.array([picker.features(a, b, 0, 4.5 * a) for a, b in zip(n, k)])
     base = np.log(1e-3 * (n.astype(float) ** 2 * k) / 4e7 + 0.05)
-    ms = np.exp(base[:, None] + r.uniform(0, 1.0, (64, 45)))
+    x1 = (np.log2(n) - 10) / 4
+    x2 = (np.log2(k) - 6.5) / 6.5
+    a, b, ph = r.normal(0, 1.5, 45), r.normal(0, 1.5, 45), r.uniform(0, 6.28, 45)
+    rel = 0.5 * np.sin(np.outer(x1, a) + np.outer(x2, b) + ph)
+    ms = np.exp(base[:, None] + rel)
     mask = np.ones_like(ms)
-    net, hist = picker.train(X, np.log(ms), mask, epochs=1500, batch=64, lr=3e-3)
+    net, hist = picker.train(X, np.log(ms), mask, epochs=3000, batch=64, lr=3e-3)
     reg, _ = picker.regret(net.predict(X), ms, mask)
     _say("memorisation: final loss %.4g, regret %s" % (hist[-1], picker.summary(reg)))
-    assert hist[-1] < hist[0] / 20
-    assert np.mean(reg) < 0.02
+    assert hist[-1] < hist[0] / 50
+    assert np.mean(reg) < 0.01
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(DATA, "tune_heldout.jsonl")),
