@@ -48,32 +48,39 @@ __device__ __forceinline__ void wave_sync() {
 // right-hand-side columns, each wave 16 of them, and holds its NP x 16 slab of
 // B in MFMA accumulator layout: fragment f, register r of lane l is row
 // 16 f + l/16 + 4 r, column l % 16 (the v_mfma_f64_16x16x4f64 result
-// layout).  The panel is solved by 16-row diagonal blocks:
-//   1. the operands of this block's updates are requested from the packed
-//      triangle (global memory) first, so they arrive during step 2;
-//   2. the 16 x 16 block of each column is gathered into one lane (every
+// layout).  The lower triangle of the packed diagonal block is staged in LDS
+// once, as 16 x 16 blocks (all loads issued together).  Then the panel is
+// solved by 16-row diagonal blocks:
+//   1. the 16 x 16 block of each column is gathered into one lane (every
 //      lane of the column's four lane groups gets the whole column, through
-//      LDS) and solved there by substitution, one IEEE division per row,
-//      reading the diagonal block from LDS;
-//   3. each lane keeps its own four rows of the result;
-//   4. every later 16-row fragment is updated on the matrix cores,
+//      LDS) and solved there by substitution, one IEEE division per row;
+//   2. each lane keeps its own four rows of the result;
+//   3. every later 16-row fragment is updated on the matrix cores,
 //      frag_p -= L_ps X_s, whose B operand for k-slice kk is exactly register
 //      kk of the solved fragment, so no data moves for the update.
-// After the diagonal blocks are staged the four waves run independently.
+// After staging, the four waves run independently.
 template <typename TS, int NP, bool UNIT, bool FULL>
 __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P, int rows,
                                                         TS* __restrict__ B, int64_t off,
                                                         int64_t br, int64_t bc, int64_t ncols) {
     constexpr int NF = NP / 16;
-    __shared__ double Ds[NF][16 * 16];  // diagonal block f, element (j, i) at Ds[f][i*16 + j]
+    constexpr int NO = NF * (NF - 1) / 2;  // strictly lower 16 x 16 blocks
+    // block (p, s), p >= s, element (row j, column i) at [i*16 + j]:
+    // diagonal blocks first, then (p, s), p > s, at NF + p(p-1)/2 + s
+    __shared__ double Ls[(NF + NO) * 256];
     __shared__ double Xs[4][16][17];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
     {
-        TS t[NF];
+        TS t[NF + NO];
 #pragma unroll
         for (int f = 0; f < NF; ++f) t[f] = P[(16 * f + tid / 16) * NP + 16 * f + tid % 16];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) Ds[f][tid] = (double)t[f];
+        for (int p = 1; p < NF; ++p)
+#pragma unroll
+            for (int q = 0; q < p; ++q)
+                t[NF + p * (p - 1) / 2 + q] = P[(16 * q + tid / 16) * NP + 16 * p + tid % 16];
+#pragma unroll
+        for (int b = 0; b < NF + NO; ++b) Ls[b * 256 + tid] = (double)t[b];
     }
     const int64_t col = (int64_t)blockIdx.x * 64 + w * 16 + c;
     const bool colok = col < ncols;
@@ -89,14 +96,7 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < NF; ++s) {
-        // 1. operands of the updates below this block
-        double ap[NF][4];
-#pragma unroll
-        for (int p = s + 1; p < NF; ++p)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                ap[p][kk] = -(double)P[(16 * s + 4 * kk + g) * NP + 16 * p + c];
-        // 2. gather the 16 rows of this block for column c into every lane
+        // 1. gather the 16 rows of this block for column c into every lane
 #pragma unroll
         for (int r = 0; r < 4; ++r) Xs[w][g + 4 * r][c] = fr[s][r];
         wave_sync();
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
         // substitution on the 16 x 16 diagonal block (axpy order).  Column
         // i+1 of the block is read from LDS while column i is applied, so
         // the chain of a step is one division and one fused multiply-add.
-        const double* Lb = Ds[s];
+        const double* Lb = Ls + s * 256;
         double cur[16], nxt[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) cur[j] = Lb[j];
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
 #pragma unroll
             for (int j = i + 1; j < 16; ++j) cur[j] = nxt[j];
         }
-        // 3. keep this lane's rows g + 4r of the solved block
+        // 2. keep this lane's rows g + 4r of the solved block
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];
@@ -135,12 +135,16 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
             fr[s][r] = g < 2 ? v01 : v23;
         }
         wave_sync();  // every lane has read Xs before the next block writes it
-        // 4. matrix-core update of the fragments below
+        // 3. matrix-core update of the fragments below; A operand for
+        // k-slice kk: element (16p + c, 16s + 4kk + g) of the triangle
 #pragma unroll
-        for (int p = s + 1; p < NF; ++p)
+        for (int p = s + 1; p < NF; ++p) {
+            const double* Lo = Ls + (NF + p * (p - 1) / 2 + s) * 256;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
-                fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[p][kk], fr[s][kk], fr[p], 0, 0, 0);
+                fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lo[(4 * kk + g) * 16 + c], fr[s][kk],
+                                                             fr[p], 0, 0, 0);
+        }
     }
     if (colok) {
 #pragma unroll
