@@ -337,6 +337,211 @@ hipError_t gemm_shortk_launch(const GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// FP64 product with operands brought straight from memory into LDS.
+//
+// buffer_load_dwordx4 ... lds writes 16 bytes per lane to LDS at M0 + 16 *
+// lane, without passing through registers, and a lane whose byte offset lies
+// past the buffer's record count receives zeros.  That removes the register
+// staging, the LDS store phase and the bounds branches of gemm_tile: per
+// k-stage a wave issues a handful of such loads for the NEXT stage right after
+// the barrier and then runs the current stage's MFMAs, and one barrier per
+// stage (whose wait for outstanding loads is what makes the next stage
+// visible) is the only synchronisation.  The MFMAs of a stage's last k-step
+// run after the barrier, on fragments read before it, so the matrix pipe is
+// still busy while the waves meet.
+//
+// Each 16-byte lane load is a pair of consecutive elements, so an operand is
+// staged in one of two layouts, chosen by which index is contiguous in memory:
+//  * w-major (pairs along the m or j index): one row of BW elements per k,
+//    rows padded by 16 elements so rows k and k+1 fall on opposite halves of
+//    the 64 banks;
+//  * k-major (pairs along k): 1 KB chunks of 8 columns x 16 k; within a chunk
+//    the pair slot of column wl is XOR-swizzled so that the 32 lanes of one
+//    half-wave fragment read (16 columns, one k pair) hit every bank once.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+constexpr unsigned kDmaOob = 0x7FFFFFF0u;  // byte offset at the record count: reads zero
+constexpr int kDmaBk = 16;
+
+template <int BW, bool KMAJOR>
+struct DmaOp {
+    static constexpr int ROW = BW + 16;                          // w-major row, elements
+    static constexpr int BYTES = KMAJOR ? BW * kDmaBk * 8 : kDmaBk * ROW * 8;
+    static constexpr int CHUNKS = BW * kDmaBk / 128;             // 1 KB loads per stage
+    static constexpr int PER_ROW = BW / 128;                     // w-major chunks per k row
+    static_assert(BW % 128 == 0, "operand width");
+    // swizzled pair slot of column wl of chunk c (k-major)
+    static __device__ __forceinline__ int swz(int wl, int c) { return ((wl >> 1) << 1) ^ (c & 1); }
+    // Issue the loads of chunk q of a stage.  p points at element (k0, w0) of
+    // the operand, whose (k, w) element is p[w + k*ld] (w-major) or
+    // p[k + w*ld] (k-major); wlim and klim are the in-range extents from there.
+    static __device__ __forceinline__ void load(const double* p, int64_t ld, int64_t wlim,
+                                                int64_t klim, char* lds, int q, int lane) {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)kDmaOob, 0x00020000);
+        unsigned voff;
+        char* dst;
+        if (!KMAJOR) {
+            const int k = q / PER_ROW, h = q % PER_ROW;
+            const int w = h * 128 + 2 * lane;
+            voff = (w < wlim && k < klim) ? (unsigned)((w + k * ld) * 8) : kDmaOob;
+            dst = lds + k * ROW * 8 + h * 1024;
+        } else {
+            const int wl = lane >> 3, kp = (lane & 7) ^ swz(wl, q);
+            const int w = 8 * q + wl;
+            voff = (w < wlim && 2 * kp < klim) ? (unsigned)((2 * kp + w * ld) * 8) : kDmaOob;
+            dst = lds + q * 1024;
+        }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 16, voff, 0, 0, 0);
+    }
+    // Element offset (doubles) of (k = 4*ks + lane/16, w = wb + 16*f + lane%16)
+    // without the f term: the fragment f adds fstride() elements.
+    static __device__ __forceinline__ int frag_off(int ks, int wb, int lane) {
+        const int g = lane >> 4, cc = lane & 15;
+        if (!KMAJOR) return (4 * ks + g) * ROW + wb + cc;
+        const int wl = cc & 7, c = (wb >> 3) + (cc >> 3);
+        const int kp = 2 * ks + (g >> 1);
+        return c * 128 + (wl * 8 + (kp ^ swz(wl, c))) * 2 + (g & 1);
+    }
+    static constexpr int fstride() { return KMAJOR ? 256 : 16; }
+};
+
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT>
+struct DmaCfg {
+    static constexpr int NW = WM * WN, NT = 64 * NW, SM = BM / WM, SN = BN / WN;
+    static constexpr int FM = SM / 16, FN = SN / 16;
+    typedef DmaOp<BM, AT> OA;   // A's contiguous index is m unless transposed
+    typedef DmaOp<BN, !RT> OX;  // X's contiguous index is k unless transposed
+    static constexpr int STAGE = OA::BYTES + OX::BYTES;
+    static_assert(OA::CHUNKS % NW == 0 && OX::CHUNKS % NW == 0, "chunks per wave");
+    static_assert(SM % 16 == 0 && SN % 16 == 0, "wave tile");
+};
+
+template <typename D, bool AT, bool RT>
+__device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0,
+                                          char* st, int wave, int lane) {
+    const double* a = (const double*)g.a;
+    const double* x = (const double*)g.x;
+    const double* pa = AT ? a + k0 + m0 * g.lda : a + m0 + k0 * g.lda;
+    const double* px = RT ? x + n0 + k0 * g.ldx : x + k0 + n0 * g.ldx;
+    const int64_t mlim = g.M - m0, nlim = g.N - n0, klim = g.K - k0;
+#pragma unroll
+    for (int i = 0; i < D::OA::CHUNKS / D::NW; ++i)
+        D::OA::load(pa, g.lda, mlim, klim, st, i * D::NW + wave, lane);
+#pragma unroll
+    for (int i = 0; i < D::OX::CHUNKS / D::NW; ++i)
+        D::OX::load(px, g.ldx, nlim, klim, st + D::OA::BYTES, i * D::NW + wave, lane);
+}
+
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT>
+__global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g) {
+    typedef DmaCfg<BM, BN, WM, WN, MINB, AT, RT> D;
+    __shared__ __attribute__((aligned(1024))) char smem[2 * D::STAGE];
+    const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+    int64_t tm, tn;
+    tile_coords(tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave % WM, wn = wave / WM;
+    int oa[4], ox[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        oa[ks] = D::OA::frag_off(ks, wm * D::SM, lane);
+        ox[ks] = D::OX::frag_off(ks, wn * D::SN, lane);
+    }
+    v4d acc[D::FM][D::FN];
+#pragma unroll
+    for (int i = 0; i < D::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < D::FN; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+
+    const int64_t ke = (g.K + kDmaBk - 1) / kDmaBk;
+    dma_stage<D, AT, RT>(g, m0, n0, 0, smem, wave, lane);
+    __syncthreads();
+    double la[D::FM], lx[D::FN];  // fragments of the last k-step, used after the barrier
+    for (int64_t kt = 0; kt < ke; ++kt) {
+        char* st = smem + (kt & 1) * D::STAGE;
+        const double* sa = (const double*)st;
+        const double* sx = (const double*)(st + D::OA::BYTES);
+        if (kt + 1 < ke)
+            dma_stage<D, AT, RT>(g, m0, n0, (kt + 1) * kDmaBk, smem + ((kt + 1) & 1) * D::STAGE,
+                                 wave, lane);
+        if (kt > 0) {
+#pragma unroll
+            for (int i = 0; i < D::FM; ++i)
+#pragma unroll
+                for (int j = 0; j < D::FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[i], lx[j], acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks) {
+            double fa[D::FM], fx[D::FN];
+#pragma unroll
+            for (int i = 0; i < D::FM; ++i) fa[i] = sa[oa[ks] + i * D::OA::fstride()];
+#pragma unroll
+            for (int j = 0; j < D::FN; ++j) fx[j] = sx[ox[ks] + j * D::OX::fstride()];
+#pragma unroll
+            for (int i = 0; i < D::FM; ++i)
+#pragma unroll
+                for (int j = 0; j < D::FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fx[j], acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < D::FM; ++i) la[i] = sa[oa[3] + i * D::OA::fstride()];
+#pragma unroll
+        for (int j = 0; j < D::FN; ++j) lx[j] = sx[ox[3] + j * D::OX::fstride()];
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0; i < D::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < D::FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[i], lx[j], acc[i][j], 0, 0, 0);
+
+    double* c = (double*)g.c;
+#pragma unroll
+    for (int i = 0; i < D::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < D::FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = m0 + wm * D::SM + i * 16 + (lane >> 4) + 4 * r;
+                const int64_t gj = n0 + wn * D::SN + j * 16 + (lane & 15);
+                if (gi < g.M && gj < g.N) {
+                    double* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
+                    *p = *p - acc[i][j][r];
+                }
+            }
+}
+
+// Shapes the direct-to-LDS kernel accepts: every index that is loaded in
+// pairs is even, leading dimensions are even and operands 16-byte aligned (so
+// a pair never straddles the end of a row or column), and one stage of each
+// operand spans less than the 2 GB byte-offset range of a buffer load.
+template <int BM, int BN, bool AT, bool RT>
+bool dma_ok(const GemmArgs& g) {
+    if ((g.lda | g.ldx) & 1) return false;
+    if (((uintptr_t)g.a | (uintptr_t)g.x) & 15) return false;
+    if (g.K & 1) return false;                   // k pairs (A^T or X) and k tails
+    if (!AT && (g.M & 1)) return false;          // m pairs
+    if (RT && (g.N & 1)) return false;           // j pairs
+    const int64_t lim = (int64_t)1 << 30;
+    const int64_t sa = AT ? (kDmaBk + (BM - 1) * g.lda) * 8 : (BM + (kDmaBk - 1) * g.lda) * 8;
+    const int64_t sx = RT ? (BN + (kDmaBk - 1) * g.ldx) * 8 : (kDmaBk + (BN - 1) * g.ldx) * 8;
+    return sa < lim && sx < lim;
+}
+
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT>
+hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s) {
+    const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT>), dim3((unsigned)tiles),
+                       dim3(64 * WM * WN), 0, s, g);
+    return hipGetLastError();
+}
+
 template <typename C, bool AT, bool RT, int TRI, bool UNIT>
 __global__ __launch_bounds__(C::NT, C::MINB) void residual_kernel(GemmArgs g, double alpha) {
     __shared__ Smem<double, C> sm;
@@ -384,7 +589,19 @@ typedef Cfg<64, 128, 16, 2, 2, 2> Tile4;   // short M, wide N
 typedef Cfg<256, 128, 16, 4, 2, 1> Tile5;  // eight waves
 typedef Cfg<64, 64, 16, 2, 2, 4> Tile6;    // small tiles, four workgroups per CU
 typedef Cfg<64, 128, 32, 2, 2, 1> Tile7;   // short M, wide N, deeper k-stage
-constexpr int kTiles = 10;  // 8: short-K 64x64, 9: short-K 32x64
+typedef Cfg<256, 128, 8, 4, 2, 2> Tile10;  // eight waves, short k-stage
+// 8: short-K 64x64, 9: short-K 32x64; FP64 direct-to-LDS: 11: 256x128 on
+// eight waves, 12: 128x128 on four waves (two workgroups per CU)
+constexpr int kTiles = 13;
+
+// Direct-to-LDS FP64 tiles where the shape allows them, else the register-
+// staged tile of the same size.
+template <typename T, int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, typename Fallback>
+hipError_t gemm_dma_or(const GemmArgs& g, hipStream_t s) {
+    if (sizeof(T) == 8 && dma_ok<BM, BN, AT, RT>(g))
+        return gemm_dma_launch_f64<BM, BN, WM, WN, MINB, AT, RT>(g, s);
+    return gemm_launch_t<T, Fallback, AT, RT>(g, s);
+}
 
 template <typename T, bool AT, bool RT>
 hipError_t gemm_by_tile(int tile, const GemmArgs& g, hipStream_t s) {
@@ -399,6 +616,9 @@ hipError_t gemm_by_tile(int tile, const GemmArgs& g, hipStream_t s) {
         case 7: return gemm_launch_t<T, Tile7, AT, RT>(g, s);
         case 8: return gemm_shortk_launch<T, 64, 64, 64, AT, RT>(g, s);
         case 9: return gemm_shortk_launch<T, 32, 64, 64, AT, RT>(g, s);
+        case 10: return gemm_launch_t<T, Tile10, AT, RT>(g, s);
+        case 11: return gemm_dma_or<T, 256, 128, 4, 2, 1, AT, RT, Tile5>(g, s);
+        case 12: return gemm_dma_or<T, 128, 128, 2, 2, 2, AT, RT, Tile1>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -460,13 +680,15 @@ hipError_t launch_residual(bool a_trans, bool rhs_trans, int tri, bool unit, dou
 
 int gemm_tile_count() { return kTiles; }
 
-// Default tile for a product shape, from a sweep of the configurations on
-// MI355X (FP64, N = 8192): eight-wave 256 x 128 tiles for long K, 64 x 64
-// tiles around K = 512, the short-K kernel below that.
+// Default tile for a product shape, from sweeps of the configurations on
+// MI355X (N = 8192): the short-K kernel for small square updates, the
+// direct-to-LDS 128 x 128 tile for FP64 from M = 512, K = 256 up (it falls back
+// to the register-staged 128 x 128 tile on shapes it does not accept), and the
+// register-staged tiles otherwise.
 int gemm_default_tile(int dtype, int64_t M, int64_t N, int64_t K) {
-    (void)dtype;
     (void)N;
     if (K <= 160 && M <= 160) return 9;
+    if (dtype == 0 && M >= 512 && K >= 256) return 12;
     if (M <= 768 || K <= 384) return 3;
     return 5;
 }
