@@ -189,7 +189,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK, 4),
                      "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
-                     "kernel": "gemm_kernel<double> (product update)",
+                     "kernel": "gemm_dma_kernel (FP64 product update, all tiles)",
                      "launches_per_step": g_launch // max(1, args.steps)},
         "cpu_baseline": cpu,
     }

@@ -352,11 +352,15 @@ hipError_t gemm_shortk_launch(const GemmArgs& g, hipStream_t s) {
 // still busy while the waves meet.
 //
 // Each 16-byte lane load is a pair of consecutive elements, so an operand is
-// staged in one of two layouts, chosen by which index is contiguous in memory:
-//  * w-major (pairs along the m or j index): one row of BW elements per k,
-//    rows padded by 16 elements so rows k and k+1 fall on opposite halves of
-//    the 64 banks;
-//  * k-major (pairs along k): 1 KB chunks of 8 columns x 16 k; within a chunk
+// staged in one of three layouts, chosen by which index is contiguous in
+// memory and by the tile width BW:
+//  * w-major, BW >= 128 (pairs along the m or j index): one row of BW
+//    elements per k, rows padded by 16 elements so rows k and k+1 fall on
+//    opposite halves of the 64 banks;
+//  * w-major, BW = 64: a 1 KB load holds rows k and k+2 (k = 4a + b, b < 2),
+//    loads are 1152 bytes apart, so rows 4s + b and 4s + b + 1 again sit on
+//    opposite bank halves and a fragment's offsets stay affine in (s, f);
+//  * k-major (pairs along k): 1 KB loads of 8 columns x 16 k; within a load
 //    the pair slot of column wl is XOR-swizzled so that the 32 lanes of one
 //    half-wave fragment read (16 columns, one k pair) hit every bank once.
 // ---------------------------------------------------------------------------
@@ -366,11 +370,13 @@ constexpr int kDmaBk = 16;
 
 template <int BW, bool KMAJOR>
 struct DmaOp {
-    static constexpr int ROW = BW + 16;                          // w-major row, elements
-    static constexpr int BYTES = KMAJOR ? BW * kDmaBk * 8 : kDmaBk * ROW * 8;
+    static constexpr bool NARROW = !KMAJOR && BW == 64;
+    static constexpr int ROW = BW + 16;                          // padded w-major row, elements
     static constexpr int CHUNKS = BW * kDmaBk / 128;             // 1 KB loads per stage
-    static constexpr int PER_ROW = BW / 128;                     // w-major chunks per k row
-    static_assert(BW % 128 == 0, "operand width");
+    static constexpr int PER_ROW = BW / 128;                     // wide w-major: loads per k row
+    static constexpr int BYTES =
+        KMAJOR ? BW * kDmaBk * 8 : (NARROW ? CHUNKS * 1152 : kDmaBk * ROW * 8);
+    static_assert(KMAJOR ? BW % 8 == 0 : (BW == 64 || BW % 128 == 0), "operand width");
     // swizzled pair slot of column wl of chunk c (k-major)
     static __device__ __forceinline__ int swz(int wl, int c) { return ((wl >> 1) << 1) ^ (c & 1); }
     // Issue the loads of chunk q of a stage.  p points at element (k0, w0) of
@@ -382,16 +388,21 @@ struct DmaOp {
             __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)kDmaOob, 0x00020000);
         unsigned voff;
         char* dst;
-        if (!KMAJOR) {
-            const int k = q / PER_ROW, h = q % PER_ROW;
-            const int w = h * 128 + 2 * lane;
-            voff = (w < wlim && k < klim) ? (unsigned)((w + k * ld) * 8) : kDmaOob;
-            dst = lds + k * ROW * 8 + h * 1024;
-        } else {
+        if (KMAJOR) {
             const int wl = lane >> 3, kp = (lane & 7) ^ swz(wl, q);
             const int w = 8 * q + wl;
             voff = (w < wlim && 2 * kp < klim) ? (unsigned)((2 * kp + w * ld) * 8) : kDmaOob;
             dst = lds + q * 1024;
+        } else if (NARROW) {
+            const int k = 4 * (q >> 1) + (q & 1) + 2 * (lane >> 5);
+            const int w = 2 * (lane & 31);
+            voff = (w < wlim && k < klim) ? (unsigned)((w + k * ld) * 8) : kDmaOob;
+            dst = lds + q * 1152;
+        } else {
+            const int k = q / PER_ROW, h = q % PER_ROW;
+            const int w = h * 128 + 2 * lane;
+            voff = (w < wlim && k < klim) ? (unsigned)((w + k * ld) * 8) : kDmaOob;
+            dst = lds + k * ROW * 8 + h * 1024;
         }
         __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 16, voff, 0, 0, 0);
     }
@@ -399,6 +410,7 @@ struct DmaOp {
     // without the f term: the fragment f adds fstride() elements.
     static __device__ __forceinline__ int frag_off(int ks, int wb, int lane) {
         const int g = lane >> 4, cc = lane & 15;
+        if (NARROW) return ((g & 1) + 2 * ks) * 144 + (g >> 1) * 64 + wb + cc;
         if (!KMAJOR) return (4 * ks + g) * ROW + wb + cc;
         const int wl = cc & 7, c = (wb >> 3) + (cc >> 3);
         const int kp = 2 * ks + (g >> 1);
@@ -591,8 +603,9 @@ typedef Cfg<64, 64, 16, 2, 2, 4> Tile6;    // small tiles, four workgroups per C
 typedef Cfg<64, 128, 32, 2, 2, 1> Tile7;   // short M, wide N, deeper k-stage
 typedef Cfg<256, 128, 8, 4, 2, 2> Tile10;  // eight waves, short k-stage
 // 8: short-K 64x64, 9: short-K 32x64; FP64 direct-to-LDS: 11: 256x128 on
-// eight waves, 12: 128x128 on four waves (two workgroups per CU)
-constexpr int kTiles = 13;
+// eight waves, 12: 128x128 on four waves (two workgroups per CU), 13:
+// 128x128 on eight waves, 14: 64x64, 15: 128x64, 16: 64x128 (four waves each)
+constexpr int kTiles = 17;
 
 // Direct-to-LDS FP64 tiles where the shape allows them, else the register-
 // staged tile of the same size.
@@ -619,6 +632,10 @@ hipError_t gemm_by_tile(int tile, const GemmArgs& g, hipStream_t s) {
         case 10: return gemm_launch_t<T, Tile10, AT, RT>(g, s);
         case 11: return gemm_dma_or<T, 256, 128, 4, 2, 1, AT, RT, Tile5>(g, s);
         case 12: return gemm_dma_or<T, 128, 128, 2, 2, 2, AT, RT, Tile1>(g, s);
+        case 13: return gemm_dma_or<T, 128, 128, 4, 2, 2, AT, RT, Tile1>(g, s);
+        case 14: return gemm_dma_or<T, 64, 64, 2, 2, 4, AT, RT, Tile6>(g, s);
+        case 15: return gemm_dma_or<T, 128, 64, 2, 2, 2, AT, RT, Tile3>(g, s);
+        case 16: return gemm_dma_or<T, 64, 128, 2, 2, 2, AT, RT, Tile4>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -681,14 +698,15 @@ hipError_t launch_residual(bool a_trans, bool rhs_trans, int tri, bool unit, dou
 int gemm_tile_count() { return kTiles; }
 
 // Default tile for a product shape, from sweeps of the configurations on
-// MI355X (N = 8192): the short-K kernel for small square updates, the
-// direct-to-LDS 128 x 128 tile for FP64 from M = 512, K = 256 up (it falls back
-// to the register-staged 128 x 128 tile on shapes it does not accept), and the
-// register-staged tiles otherwise.
+// MI355X (N = 8192).  FP64: the direct-to-LDS 128 x 128 eight-wave tile once
+// M and K reach 1024, the direct-to-LDS 64 x 64 tile below that (each falls
+// back to a register-staged tile on shapes the direct path does not accept).
+// FP32: the short-K kernel for small square updates, 64 x 64 tiles for short
+// M or K, the eight-wave 256 x 128 tile otherwise.
 int gemm_default_tile(int dtype, int64_t M, int64_t N, int64_t K) {
     (void)N;
+    if (dtype == 0) return (M >= 1024 && K >= 1024) ? 13 : 14;
     if (K <= 160 && M <= 160) return 9;
-    if (dtype == 0 && M >= 512 && K >= 256) return 12;
     if (M <= 768 || K <= 384) return 3;
     return 5;
 }

@@ -13,7 +13,7 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 U64, U32 = 2.0 ** -53, 2.0 ** -24
-TILES = list(range(13))
+TILES = list(range(17))
 
 
 def _run(A, X, C, transa, transx, tile, dtype):
@@ -56,18 +56,19 @@ def test_update_integer_exact(tile, dtype):
 
 @pytest.mark.parametrize("transa,transx", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_direct_lds_tiles_match_register_staged(transa, transx):
-    # Tiles 11 and 12 stage operands with direct-to-LDS loads; on shapes they
-    # accept they run the MFMA sequence of tiles 5 and 1 in the same k order,
-    # so the results agree bit for bit.  Shapes span several tiles with ragged
-    # tails in every dimension (all even, as the direct path requires).
+    # Tiles 11-16 stage operands with direct-to-LDS loads; on shapes they
+    # accept they run the same MFMA sequence in the same k order as the
+    # register-staged tile 5, so the results agree bit for bit.  Shapes span
+    # several tiles with ragged tails in every dimension (all even, as the
+    # direct path requires).
     for (M, N, K) in [(520, 390, 266), (256, 128, 16), (2, 2, 2), (258, 130, 18), (768, 256, 1024)]:
         r = synth.rng((33, M, N + K))
         A = r.standard_normal((M, K))
         X = r.standard_normal((K, N))
         C = r.standard_normal((M, N))
-        for fast, staged in [(11, 5), (12, 1)]:
+        want = _run(A, X, C, transa, transx, 5, np.float64)
+        for fast in range(11, 17):
             got = _run(A, X, C, transa, transx, fast, np.float64)
-            want = _run(A, X, C, transa, transx, staged, np.float64)
             assert np.array_equal(got, want), (M, N, K, fast)
         ref = C - A @ X
         bound = 2 * K * U64 * (np.abs(C) + np.abs(A) @ np.abs(X))
