@@ -10,12 +10,16 @@
 //   acc = alpha B_p;  acc -= L_pq X_q for every solved block q < p on the
 //   matrix cores (operands for q+1 are requested while q is multiplied);
 //   then the 16 x 16 diagonal block is solved by substitution in every lane
-//   (one IEEE division per row) and X_p is stored.
+//   (one correctly rounded division per row, from a reciprocal of the
+//   diagonal prepared while the matrix cores run) and X_p is stored.
 // A task never depends on another, so the result does not depend on which
 // wave ran it.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "batched.h"
+#include "fdiv.h"
 
 namespace redsea {
 
@@ -43,6 +47,7 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                                                       int* __restrict__ info, double alpha) {
     __shared__ double Xs[4][16][17];  // per-wave gather buffer
     __shared__ double Ls[4][16 * 16]; // per-wave diagonal block, (j, i) at [i*16 + j]
+    __shared__ double Rs[4][16];      // per-wave 1 / diagonal
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
     for (;;) {
         int t = 0;
@@ -70,6 +75,19 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = alpha * bget(16 * p + g + 4 * r);
             if (alpha != 0.0) {
+                // diagonal block (identity past the order) and the reciprocals
+                // of its diagonal; independent of the products below
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = g + 4 * r;  // row of the block, column c
+                    const int64_t gi = 16 * p + i, gj = 16 * p + c;
+                    double v = 0.0;
+                    if (gi >= k) v = (i == c) ? 1.0 : 0.0;
+                    else if (i == c) v = UNIT ? 1.0 : aget(gi, gj);
+                    else if (i > c) v = aget(gi, gj);
+                    Ls[w][c * 16 + i] = v;
+                    if (!UNIT && i == c) Rs[w][c] = 1.0 / v;
+                }
                 // acc -= L_pq X_q, q < p; operands of q+1 requested before q's MFMAs
                 double xa[4], aa[4];
                 if (p > 0) {
@@ -99,30 +117,60 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                         }
                     }
                 }
-                // diagonal block (identity past the order) and the column's rows
+                // the column's rows of the block
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = g + 4 * r;  // row of the block, column c
-                    const int64_t gi = 16 * p + i, gj = 16 * p + c;
-                    double v = 0.0;
-                    if (gi >= k) v = (i == c) ? 1.0 : 0.0;
-                    else if (i == c) v = UNIT ? 1.0 : aget(gi, gj);
-                    else if (i > c) v = aget(gi, gj);
-                    Ls[w][c * 16 + i] = v;
-                    Xs[w][i][c] = acc[r];
-                }
+                for (int r = 0; r < 4; ++r) Xs[w][g + 4 * r][c] = acc[r];
                 wave_sync();
+                // substitution (axpy order), pipelined by one row as in the
+                // leaf solver; the fast divisions are redone in IEEE
+                // arithmetic for the whole block if any operand of the wave
+                // left their guard (same result wherever it held)
                 double y[16];
+                auto subst = [&](auto fast) {
+                    double dg[16], rd[16], cur[16], nxt[16];
+                    bool dok[16];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) y[i] = Xs[w][i][c];
+                    for (int i = 0; i < 16; ++i) {
+                        y[i] = Xs[w][i][c];
+                        if (!UNIT) {
+                            dg[i] = Ls[w][i * 16 + i];
+                            rd[i] = Rs[w][i];
+                            dok[i] = div_fast_divisor(dg[i]);
+                        }
+                    }
+                    bool ok = true;
+                    auto divide = [&](double a, int i) -> double {
+                        if (UNIT) return a;
+                        if (!decltype(fast)::value) return a / dg[i];
+                        bool oki;
+                        const double q = div_rn_fast(a, dg[i], rd[i], dok[i], oki);
+                        ok = ok && oki;
+                        return q;
+                    };
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    double x = y[i];
-                    if (!UNIT) x = x / Ls[w][i * 16 + i];
-                    y[i] = x;
+                    for (int j = 1; j < 16; ++j) cur[j] = Ls[w][j];
+                    double x = divide(y[0], 0);
+                    y[0] = x;
 #pragma unroll
-                    for (int j = i + 1; j < 16; ++j) y[j] = __builtin_fma(-Ls[w][i * 16 + j], x, y[j]);
-                }
+                    for (int i = 0; i + 1 < 16; ++i) {
+#pragma unroll
+                        for (int j = i + 2; j < 16; ++j) nxt[j] = Ls[w][(i + 1) * 16 + j];
+                        const double yn = __builtin_fma(-cur[i + 1], x, y[i + 1]);
+                        const double xn = divide(yn, i + 1);
+#pragma unroll
+                        for (int j = i + 2; j < 16; ++j) y[j] = __builtin_fma(-cur[j], x, y[j]);
+                        y[i + 1] = xn;
+                        x = xn;
+#pragma unroll
+                        for (int j = i + 1; j < 16; ++j) asm volatile("" : "+v"(y[j]));
+                        asm volatile("" ::: "memory");
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int j = i + 2; j < 16; ++j) cur[j] = nxt[j];
+                    }
+                    return ok;
+                };
+                if (!__all(subst(std::true_type()))) subst(std::false_type());
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];

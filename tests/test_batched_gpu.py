@@ -83,6 +83,38 @@ def test_big_systems_and_empty_and_alpha():
             assert oracle.backward_error(0, 0, 0, 0, -2.0, A, B, X) <= 1e-14 * A.shape[0]
 
 
+def test_diagonal_systems_divide_exactly():
+    # Every row is one division x_i = b_i / d_i.  The batched solver divides
+    # through a reciprocal and two Markstein corrections, redoing a block in
+    # IEEE arithmetic when an operand leaves the fast path's range; the result
+    # must be the IEEE quotient in every case: ordinary operands, divisors
+    # 2^k with |k| up to 600, numerators from subnormal to 1e305, zeros.
+    r = synth.rng((3, 9, 9))
+    As, Bs, want = [], [], []
+    for sysid in range(5):
+        n, k = 70 + 13 * sysid, 5 + sysid
+        if sysid in (0, 3, 4):
+            d = np.diag(synth.diagonal(n, (3, 9, sysid)))
+        else:
+            d = np.ldexp(r.uniform(1.0, 2.0, n), r.integers(-600, 601, n)) * r.choice([-1.0, 1.0], n)
+        B = r.standard_normal((n, k))
+        if sysid in (2, 3):  # no quotient overflows: |b/d| < 2^1018
+            top = 300 if sysid == 2 else 1015
+            B = B * np.ldexp(1.0, r.integers(-1070, top, (n, k)).astype(np.int64))
+        if sysid == 4:
+            B[:, ::2] = 0.0
+        A = np.full((n, n), np.nan)
+        A[np.tril_indices(n, -1)] = 0.0
+        A[np.diag_indices(n)] = d
+        As.append(np.asfortranarray(A))
+        Bs.append(np.asfortranarray(B))
+        want.append(B / d[:, None])
+    Xs, info = _run(As, Bs)
+    assert np.all(info == 0)
+    for i, (X, W) in enumerate(zip(Xs, want)):
+        assert np.array_equal(X, W), i
+
+
 def test_nonfinite_system_is_flagged():
     As, Bs = _make(6, (3, 2, 2), n_range=(40, 200), nrhs_range=(2, 20))
     Bs[3] = Bs[3].copy(order="F")
