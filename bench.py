@@ -42,6 +42,25 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
+def algorithmic_bytes(n, nrhs, nb):
+    """8 (MK + KN + 2MN) summed over the product launches of the recursive
+    schedule down to leaves of nb rows, per launch (the unit of `traffic`)."""
+    total, count = 0, 0
+    def split(rows):
+        nonlocal total, count
+        if rows <= nb:
+            return
+        nblk = (rows + nb - 1) // nb
+        top = ((nblk + 1) // 2) * nb
+        bot = rows - top
+        split(top)
+        total += 8 * (bot * top + top * nrhs + 2 * bot * nrhs)
+        count += 1
+        split(bot)
+    split(n)
+    return total / max(1, count)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -189,6 +208,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK, 4),
                      "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": (round(algorithmic_bytes(n, nrhs, args.nb))
+                                                      if args.variant == "recursive" else None),
                      "kernel": "gemm_dma_kernel (FP64 product update, all tiles)",
                      "launches_per_step": g_launch // max(1, args.steps)},
         "cpu_baseline": cpu,
