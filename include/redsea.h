@@ -304,6 +304,19 @@ int redsea_pick(int dtype, int64_t n, int64_t nrhs, double kappa, int* confident
 int redsea_mlp_load(const char* path);
 
 /* Library version as "major.minor.patch". */
+/* Diagnostic, not part of the solver: the achievable matrix-core rate.
+ * Launches, asynchronously on `stream`, 4096 workgroups of four waves, each
+ * wave running eight independent chains of `iters` (rounded up to a multiple
+ * of 16) 16x16x4 MFMAs in `dtype`
+ * (REDSEA_F64 or REDSEA_F32), and writes one checksum per thread to `out`
+ * (device, caller-owned, at least 4096*256 elements of `dtype`).  Returns the
+ * number of floating-point operations performed, so that flops / elapsed time
+ * measured by the caller with events on `stream` is the achieved rate; -1 for
+ * a bad dtype or iters <= 0, -3 for a missing or short `out`, -100 when the
+ * launch fails.  The MI355X datasheet roofs are 78.6 (FP64) and 157.3 (FP32)
+ * TFLOP/s. */
+int64_t redsea_mfma_peak(int dtype, int64_t iters, void* out, int64_t out_elems, hipStream_t stream);
+
 const char* redsea_version(void);
 
 #ifdef __cplusplus

@@ -5,9 +5,9 @@ functions here only marshal arguments; the solves run in the library's HIP
 kernels for gfx950.
 """
 from ._binding import (BatchPlan, EXPORTS, KERNEL_CLASSES, LIB_PATH, trace_begin, trace_end, MixedStats, Opts, RedseaError, fortran_tensor, gemm_update, lib,
-                       mixed_workspace_bytes, schedule, status_string, trsm, trsm_batched,
+                       mfma_peak, mixed_workspace_bytes, schedule, status_string, trsm, trsm_batched,
                        trsm_mixed, version)
 
 __all__ = ["BatchPlan", "EXPORTS", "KERNEL_CLASSES", "LIB_PATH", "trace_begin", "trace_end", "MixedStats", "Opts", "RedseaError", "fortran_tensor", "gemm_update", "lib",
-           "mixed_workspace_bytes", "schedule", "status_string", "trsm", "trsm_batched",
+           "mfma_peak", "mixed_workspace_bytes", "schedule", "status_string", "trsm", "trsm_batched",
            "trsm_mixed", "version"]

@@ -37,6 +37,7 @@ EXPORTS = (
     "redsea_mlp_adam",
     "redsea_pick",
     "redsea_mlp_load",
+    "redsea_mfma_peak",
 )
 KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group")
 
@@ -75,6 +76,8 @@ def lib() -> ctypes.CDLL:
                            "(or __graft_entry__.build())")
     L = ctypes.CDLL(LIB_PATH)
     i64, dbl, ptr, cint, sz = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    L.redsea_mfma_peak.restype = i64
+    L.redsea_mfma_peak.argtypes = [cint, i64, ptr, i64, ptr]
     L.redsea_trsm.restype = cint
     L.redsea_trsm.argtypes = [cint, cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64,
                               ctypes.POINTER(Opts), ptr]
@@ -320,3 +323,28 @@ def trace_end():
     _check(lib().redsea_trace_end(ctypes.cast(la, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p),
                                   ctypes.cast(fl, ctypes.c_void_p), n))
     return {k: (int(la[i]), float(ms[i]), float(fl[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def mfma_peak(dtype: str = "f64", iters: int = 4000, reps: int = 5, stream=None) -> float:
+    """Achievable matrix-core rate in TFLOP/s (median of `reps` timed launches
+    of the library's MFMA-only probe kernel)."""
+    import torch
+    code = 0 if dtype == "f64" else 1
+    out = torch.empty(4096 * 256, dtype=torch.float64 if code == 0 else torch.float32, device="cuda")
+    s = _stream(stream)
+    st = torch.cuda.current_stream() if stream is None else stream
+    L = lib()
+    flops = L.redsea_mfma_peak(code, iters, out.data_ptr(), out.numel(), s)
+    if flops <= 0:
+        raise RedseaError(int(flops), "mfma peak probe failed")
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        L.redsea_mfma_peak(code, iters, out.data_ptr(), out.numel(), s)
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    return flops / times[len(times) // 2] / 1e12

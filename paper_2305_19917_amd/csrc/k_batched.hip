@@ -63,11 +63,23 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
         const bool colok = c < wcols;
         const int nblk = (int)((k + 15) / 16);
         const int64_t bcol = S.b_off + (c0 + (colok ? c : 0)) * S.bc;
+        // Operand reads.  FP64: predicated loads.  FP32: branch-free, an
+        // out-of-range lane reads a valid element (the first of the system or
+        // of the task's first column) and discards it; with a predicated load
+        // the widening to FP64 sits inside the branch and makes every load
+        // wait for its data before the next is issued.
+        const int64_t bsafe = S.b_off + c0 * S.bc;
         auto bget = [&](int64_t row) -> double {
-            return (colok && row < k) ? (double)B[bcol + row * S.br] : 0.0;
+            const bool ok = colok && row < k;
+            if constexpr (sizeof(TS) == 8) return ok ? (double)B[bcol + row * S.br] : 0.0;
+            const TS v = B[ok ? bcol + row * S.br : bsafe];
+            return ok ? (double)v : 0.0;
         };
         auto aget = [&](int64_t row, int64_t col) -> double {
-            return row < k ? (double)A[S.a_off + row * S.tr + col * S.tc] : 0.0;
+            const bool ok = row < k;
+            if constexpr (sizeof(TS) == 8) return ok ? (double)A[S.a_off + row * S.tr + col * S.tc] : 0.0;
+            const TS v = A[ok ? S.a_off + row * S.tr + col * S.tc : S.a_off];
+            return ok ? (double)v : 0.0;
         };
         int bad = 0;
         for (int p = 0; p < nblk; ++p) {

@@ -1,0 +1,203 @@
+"""Measurements of the solver on the workloads it is specified for, one JSON
+line per result (python -m paper_2305_19917_amd.measure [rows ...]).
+
+Rows:
+  peak     achievable FP64/FP32 MFMA rate (the library's MFMA-only probe),
+           device-to-device copy bandwidth, and the vendor FP64 GEMM
+           (torch.matmul) as an achievable-GEMM reference
+  small    FP64 lower/N/non-unit, n = 512, nrhs = 64: microseconds per solve
+  thin     FP64 n = 8192, nrhs = 1024: upper/transposed and lower/unit-diagonal
+           (diagonal stored as NaN), plus lower/N for nrhs in {1, 8, 32}, with
+           the HBM rate implied by the algorithmic bytes
+  mixed    FP64 in/out, n = 16384, nrhs = 4096, conditioning family with
+           kappa_1 in {1e2, 1e4, 1e6}: plain FP64 against FP32 + FP64 refinement
+           and BF16 + FP64 refinement (effective TFLOP/s of the whole call,
+           iterations and the library's own final backward error)
+  batched  2000 systems, n log-uniform in [32, 1024], nrhs in [1, 256], FP64
+           and FP32, one plan launch (eager and hipGraph replay)
+
+Timing: hipEvents on the stream, B restored by a device copy outside the
+events, median of the repetitions.  Inputs are the seeded synthetic systems of
+the `synth` module.  Accuracy is checked by the tests, not here.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _emit(rec):
+    print(json.dumps(rec), flush=True)
+
+
+def _time(fn, restore, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    restore()
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        restore()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn()
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def row_peak():
+    import torch
+    import paper_2305_19917_amd as rs
+    rec = {"row": "peak", "mfma_f64_tflops": round(rs.mfma_peak("f64"), 2),
+           "mfma_f32_tflops": round(rs.mfma_peak("f32"), 2),
+           "datasheet_f64_tflops": 78.6, "datasheet_f32_tflops": 157.3, "datasheet_hbm_tbs": 8.0}
+    n = 1 << 27  # 1 GiB of doubles
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    ms = _time(lambda: b.copy_(a), lambda: None, 10)
+    rec["copy_tbs"] = round(2 * 8 * n / (ms * 1e-3) / 1e12, 3)
+    del a, b
+    for m in (4096, 8192):
+        x = torch.randn(m, m, dtype=torch.float64, device="cuda")
+        y = torch.randn(m, m, dtype=torch.float64, device="cuda")
+        ms = _time(lambda: torch.matmul(x, y), lambda: None, 5)
+        rec["torch_dgemm_%d_tflops" % m] = round(2.0 * m ** 3 / (ms * 1e-3) / 1e12, 2)
+        del x, y
+    torch.cuda.empty_cache()
+    _emit(rec)
+
+
+def row_small():
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    n, nrhs = 512, 64
+    L = synth.dominant_lower(n, (0, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (0, 0, 1))
+    dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
+    dB = dB0.t().clone().t()
+    out = {"row": "small", "n": n, "nrhs": nrhs}
+    for variant, nb in (("recursive", 64), ("recursive", 128), ("iterative", 128), ("blocked", 64)):
+        ms = _time(lambda: rs.trsm(dL, dB, variant=variant, nb=nb), lambda: dB.copy_(dB0), 200)
+        out["%s_nb%d_us" % (variant, nb)] = round(ms * 1e3, 2)
+    _emit(out)
+
+
+def row_thin():
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    n = 8192
+    L = synth.dominant_lower(n, (1, 0, 0))
+    dL = rs.fortran_tensor(L)
+
+    def report(tag, nrhs, A, side_args, reps):
+        B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+        dB0 = rs.fortran_tensor(B)
+        dB = dB0.t().clone().t()
+        ms = _time(lambda: rs.trsm(A, dB, *side_args, variant="recursive", nb=128),
+                   lambda: dB.copy_(dB0), reps)
+        flops = float(n) * n * nrhs
+        byts = 8.0 * (n * (n + 1) / 2 + 2.0 * n * nrhs)
+        _emit({"row": "thin", "case": tag, "n": n, "nrhs": nrhs, "ms": round(ms, 4),
+               "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+               "algorithmic_gbs": round(byts / (ms * 1e-3) / 1e9, 1),
+               "roof_ms_fp64": round(flops / 78.6e12 * 1e3, 4), "roof_ms_hbm": round(byts / 8e12 * 1e3, 4)})
+
+    U = np.asfortranarray(L.T)
+    dU = rs.fortran_tensor(U)
+    report("left upper T", 1024, dU, ("L", "U", "T", "N"), 10)
+    del dU
+    Lu = synth.unit_lower(n, (1, 0, 0))
+    dLu = rs.fortran_tensor(Lu)
+    report("left lower N unit", 1024, dLu, ("L", "L", "N", "U"), 10)
+    del dLu
+    for nrhs in (1, 8, 32, 1024):
+        report("left lower N", nrhs, dL, ("L", "L", "N", "N"), 10)
+
+
+def row_mixed():
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "kappa_family.json")))
+    n, nrhs = 16384, 4096
+    for e in [x for x in tab["entries"] if x["n"] == n]:
+        L = synth.kappa_lower(n, e["c"], tuple(tab["key"]))
+        B = synth.rhs_normal(n, nrhs, (2, 0, 1))
+        dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
+        dB = dB0.t().clone().t()
+        rec = {"row": "mixed", "n": n, "nrhs": nrhs, "kappa_target": e["target"], "kappa1": e["kappa1"]}
+        for name, fn in (("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=128)),
+                         ("fp32_ir", lambda: rs.trsm_mixed(dL, dB, inner=1)),
+                         ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2))):
+            ms = _time(fn, lambda: dB.copy_(dB0), 3)
+            dB.copy_(dB0)
+            st = fn()
+            torch.cuda.synchronize()
+            r = {"ms": round(ms, 3), "tflops_eff": round(float(n) * n * nrhs / (ms * 1e-3) / 1e12, 3)}
+            if isinstance(st, rs.MixedStats):
+                r.update({"iterations": st.iterations, "eta": st.eta, "fell_back": st.fell_back})
+            rec[name] = r
+        _emit(rec)
+        del dL, dB0, dB
+        torch.cuda.empty_cache()
+
+
+def row_batched():
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    ns, ks = synth.batch_shapes(2000, (3, 0, 2))
+    flops = float((ns.astype(float) ** 2 * ks).sum())
+    for dt, es in ((np.float64, 8), (np.float32, 4)):
+        byts = float(sum(es * (n * (n + 1) / 2 + 2.0 * n * k) for n, k in zip(ns, ks)))
+        As = [rs.fortran_tensor(synth.dominant_lower(int(n), (3, i, 0)).astype(dt)) for i, n in enumerate(ns)]
+        Bs = [rs.fortran_tensor(synth.rhs_normal(int(n), int(k), (3, i, 1)).astype(dt))
+              for i, (n, k) in enumerate(zip(ns, ks))]
+        info = torch.zeros(len(Bs), dtype=torch.int32, device="cuda")
+        plan = rs.BatchPlan(As, Bs)
+        ms = _time(lambda: plan.run(info), lambda: None, 20)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=s):
+            plan.run(info, stream=s)
+        torch.cuda.synchronize()
+        gms = _time(lambda: g.replay(), lambda: None, 20)
+        _emit({"row": "batched", "dtype": np.dtype(dt).name, "systems": len(Bs), "ms": round(ms, 4),
+               "graph_ms": round(gms, 4), "systems_per_s": round(len(Bs) / (gms * 1e-3)),
+               "tflops": round(flops / (gms * 1e-3) / 1e12, 3),
+               "algorithmic_gbs": round(byts / (gms * 1e-3) / 1e9, 1),
+               "info_nonzero": int((info != 0).sum().item())})
+        plan.close()
+        del As, Bs, g
+        torch.cuda.empty_cache()
+
+
+ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "mixed": row_mixed,
+        "batched": row_batched}
+
+
+def main(argv):
+    names = argv or list(ROWS)
+    for name in names:
+        t0 = time.perf_counter()
+        print("# row %s" % name, file=sys.stderr, flush=True)
+        ROWS[name]()
+        print("# row %s done in %.1f s" % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
