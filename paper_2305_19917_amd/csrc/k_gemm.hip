@@ -446,13 +446,30 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
         D::OX::load(px, g.ldx, nlim, klim, st + D::OA::BYTES, i * D::NW + wave, lane);
 }
 
-template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT>
-__global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g) {
+// TRI = 0: C -= A X.  TRI = 1 / 2: A is the lower / upper triangle of its
+// storage (the other triangle is never used, whatever it holds; with UNIT the
+// diagonal is taken as 1) and C := alpha_c C - A X, the residual of a
+// triangular solve.  Only the k-stages that meet the triangle in rows
+// [m0, m0 + BM) are run, and in the stages that cross the diagonal the A
+// fragments are masked after they are read from LDS.
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false>
+__global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g, double alpha_c) {
     typedef DmaCfg<BM, BN, WM, WN, MINB, AT, RT> D;
     __shared__ __attribute__((aligned(1024))) char smem[2 * D::STAGE];
     const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
     int64_t tm, tn;
-    tile_coords(tiles_m, tiles_n, tm, tn);
+    if (TRI == 0) {
+        tile_coords(tiles_m, tiles_n, tm, tn);
+    } else {
+        // Triangle: a row tile's work grows with its distance into the
+        // triangle.  Rows are taken heaviest first, and consecutive
+        // workgroups walk along a row, so the round-robin dispatch over the
+        // XCDs gives each XCD an equal share of every row (and a fixed set of
+        // X column panels).
+        const int64_t r = (int64_t)blockIdx.x / tiles_n;
+        tn = (int64_t)blockIdx.x % tiles_n;
+        tm = TRI == 1 ? tiles_m - 1 - r : r;
+    }
     const int64_t m0 = tm * BM, n0 = tn * BN;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -469,18 +486,36 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
 #pragma unroll
         for (int j = 0; j < D::FN; ++j) acc[i][j] = v4d{0, 0, 0, 0};
 
-    const int64_t ke = (g.K + kDmaBk - 1) / kDmaBk;
-    dma_stage<D, AT, RT>(g, m0, n0, 0, smem, wave, lane);
+    // k-stages [kb, ke): all of K, or those meeting the triangle
+    int64_t kb = 0, ke = (g.K + kDmaBk - 1) / kDmaBk;
+    if (TRI == 1) {
+        const int64_t last = m0 + BM < g.K ? m0 + BM : g.K;
+        ke = (last + kDmaBk - 1) / kDmaBk;
+    } else if (TRI == 2) {
+        kb = m0 / kDmaBk;
+    }
+    // triangle mask of an A fragment element: row m0 + wm*SM + 16 i + lane%16,
+    // column k0 + 4 ks + lane/16
+    const int64_t mrow = m0 + wm * D::SM + (lane & 15);
+    auto mask = [&](double v, int i, int64_t kcol) -> double {
+        const int64_t m = mrow + 16 * i;
+        const bool inside = TRI == 1 ? kcol <= m : kcol >= m;
+        return inside ? ((UNIT && kcol == m) ? 1.0 : v) : 0.0;
+    };
+    if (kb < ke) dma_stage<D, AT, RT>(g, m0, n0, kb * kDmaBk, smem + (kb & 1) * D::STAGE, wave, lane);
     __syncthreads();
     double la[D::FM], lx[D::FN];  // fragments of the last k-step, used after the barrier
-    for (int64_t kt = 0; kt < ke; ++kt) {
+    for (int64_t kt = kb; kt < ke; ++kt) {
         char* st = smem + (kt & 1) * D::STAGE;
         const double* sa = (const double*)st;
         const double* sx = (const double*)(st + D::OA::BYTES);
+        const int64_t k0 = kt * kDmaBk;
+        // a stage crossing the diagonal of this row tile (uniform)
+        const bool diag = TRI != 0 && k0 + kDmaBk > m0 && k0 < m0 + BM;
         if (kt + 1 < ke)
             dma_stage<D, AT, RT>(g, m0, n0, (kt + 1) * kDmaBk, smem + ((kt + 1) & 1) * D::STAGE,
                                  wave, lane);
-        if (kt > 0) {
+        if (kt > kb) {
 #pragma unroll
             for (int i = 0; i < D::FM; ++i)
 #pragma unroll
@@ -492,6 +527,10 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
             double fa[D::FM], fx[D::FN];
 #pragma unroll
             for (int i = 0; i < D::FM; ++i) fa[i] = sa[oa[ks] + i * D::OA::fstride()];
+            if (TRI != 0 && diag) {
+#pragma unroll
+                for (int i = 0; i < D::FM; ++i) fa[i] = mask(fa[i], i, k0 + 4 * ks + (lane >> 4));
+            }
 #pragma unroll
             for (int j = 0; j < D::FN; ++j) fx[j] = sx[ox[ks] + j * D::OX::fstride()];
 #pragma unroll
@@ -502,16 +541,22 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
         }
 #pragma unroll
         for (int i = 0; i < D::FM; ++i) la[i] = sa[oa[3] + i * D::OA::fstride()];
+        if (TRI != 0 && diag) {
+#pragma unroll
+            for (int i = 0; i < D::FM; ++i) la[i] = mask(la[i], i, k0 + 12 + (lane >> 4));
+        }
 #pragma unroll
         for (int j = 0; j < D::FN; ++j) lx[j] = sx[ox[3] + j * D::OX::fstride()];
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
     }
+    if (kb < ke) {
 #pragma unroll
-    for (int i = 0; i < D::FM; ++i)
+        for (int i = 0; i < D::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < D::FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[i], lx[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < D::FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[i], lx[j], acc[i][j], 0, 0, 0);
+    }
 
     double* c = (double*)g.c;
 #pragma unroll
@@ -524,7 +569,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
                 const int64_t gj = n0 + wn * D::SN + j * 16 + (lane & 15);
                 if (gi < g.M && gj < g.N) {
                     double* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    *p = *p - acc[i][j][r];
+                    *p = (TRI == 0 ? *p : alpha_c * *p) - acc[i][j][r];
                 }
             }
 }
@@ -546,11 +591,11 @@ bool dma_ok(const GemmArgs& g) {
     return sa < lim && sx < lim;
 }
 
-template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT>
-hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s) {
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false>
+hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s, double alpha_c = 1.0) {
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT>), dim3((unsigned)tiles),
-                       dim3(64 * WM * WN), 0, s, g);
+    hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT, TRI, UNIT>),
+                       dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, alpha_c);
     return hipGetLastError();
 }
 
@@ -673,6 +718,10 @@ hipError_t gemm_group_any(int tile, bool at, bool rt, const GemmGroup& grp, hipS
 
 template <bool AT, bool RT, int TRI>
 hipError_t residual_u(bool unit, const GemmArgs& g, double alpha, hipStream_t s) {
+    // direct-to-LDS 128 x 128 tile on eight waves where the shape allows it
+    if (dma_ok<128, 128, AT, RT>(g))
+        return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true>(g, s, alpha)
+                    : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false>(g, s, alpha);
     return unit ? residual_launch<Tile5, AT, RT, TRI, true>(g, alpha, s)
                 : residual_launch<Tile5, AT, RT, TRI, false>(g, alpha, s);
 }

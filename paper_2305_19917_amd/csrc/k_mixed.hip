@@ -126,20 +126,60 @@ __global__ __launch_bounds__(256) void rowmax_kernel(const double* __restrict__ 
     out[i] = mx;
 }
 
-// out[i] = sum_j |M(i, j)| over the triangle of M (row sums; the infinity
-// norm of M is their maximum).  M(i, j) = a[i + j*lda] or a[j + i*lda].
-__global__ __launch_bounds__(256) void tri_rowsum_kernel(const double* __restrict__ a, int64_t lda,
-                                                         int64_t k, int a_trans, int lower,
-                                                         int unit, double* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= k) return;
-    double sum = 0.0;
-    const int64_t j0 = lower ? 0 : i, j1 = lower ? i + 1 : k;
-    for (int64_t j = j0; j < j1; ++j) {
-        const double v = (j == i && unit) ? 1.0 : (a_trans ? a[j + i * lda] : a[i + j * lda]);
-        sum += fabs(v);
+// Row sums of |T| for ||T||_inf (T the canonical triangle, unit diagonal as
+// 1).  Storage not transposed: a row of T runs across columns, so a
+// workgroup takes 64 rows (one per lane, coalesced reads down each column)
+// and its eight waves split the columns the triangle covers; the partial sums
+// are added in a fixed order.  Transposed: a row is contiguous in storage and
+// one wave sums it, lanes striding along it, then a fixed shuffle tree.
+__global__ __launch_bounds__(512) void tri_rowsum_rows_kernel(const double* __restrict__ a,
+                                                              int64_t lda, int64_t k, int lower,
+                                                              int unit, double* __restrict__ out) {
+    __shared__ double part[8][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64, i = r0 + lane;
+    const int64_t jlo = lower ? 0 : r0, jhi = lower ? (r0 + 64 < k ? r0 + 64 : k) : k;
+    const int64_t per = (jhi - jlo + 7) / 8;
+    const int64_t ja = jlo + w * per, jb = ja + per < jhi ? ja + per : jhi;
+    auto term = [&](int64_t j) -> double {
+        const bool in = lower ? j <= i : j >= i;
+        if (!in) return 0.0;
+        return (unit && j == i) ? 1.0 : __builtin_fabs(a[i + j * lda]);
+    };
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < k) {
+        int64_t j = ja;
+        for (; j + 4 <= jb; j += 4) {
+            s0 += term(j);
+            s1 += term(j + 1);
+            s2 += term(j + 2);
+            s3 += term(j + 3);
+        }
+        for (; j < jb; ++j) s0 += term(j);
     }
-    out[i] = sum;
+    part[w][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (w == 0 && i < k) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += part[q][lane];
+        out[i] = t;
+    }
+}
+
+__global__ __launch_bounds__(512) void tri_rowsum_trans_kernel(const double* __restrict__ a,
+                                                               int64_t lda, int64_t k, int lower,
+                                                               int unit, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 8 + w;
+    if (i >= k) return;  // uniform over the wave
+    const int64_t jlo = lower ? 0 : i, jhi = lower ? i + 1 : k;
+    const double* row = a + i * lda;  // element (i, j) of T at row[j]
+    double s = 0.0;
+    for (int64_t j = jlo + lane; j < jhi; j += 64) s += (unit && j == i) ? 1.0 : __builtin_fabs(row[j]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[i] = s;
 }
 
 // ------------------------------------------------------------------ BF16 product
@@ -277,8 +317,12 @@ hipError_t launch_rhs_max(const double* a, int64_t ld, int64_t m, int64_t n, boo
 hipError_t launch_tri_rowsum(const double* a, int64_t lda, int64_t k, bool a_trans, bool lower,
                              bool unit, double* out, hipStream_t s) {
     if (k <= 0) return hipSuccess;
-    hipLaunchKernelGGL(tri_rowsum_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, a,
-                       lda, k, a_trans ? 1 : 0, lower ? 1 : 0, unit ? 1 : 0, out);
+    if (!a_trans)
+        hipLaunchKernelGGL(tri_rowsum_rows_kernel, dim3((unsigned)((k + 63) / 64)), dim3(512), 0, s,
+                           a, lda, k, lower ? 1 : 0, unit ? 1 : 0, out);
+    else
+        hipLaunchKernelGGL(tri_rowsum_trans_kernel, dim3((unsigned)((k + 7) / 8)), dim3(512), 0, s,
+                           a, lda, k, lower ? 1 : 0, unit ? 1 : 0, out);
     return hipGetLastError();
 }
 

@@ -70,6 +70,9 @@ def test_all_flags_backward_error(side, uplo, trans, diag):
     k, nrhs = 400, 30
     L = synth.unit_lower(k, (16, k, 0)) if diag else synth.dominant_lower(k, (16, k, 0))
     A = np.array(L if uplo == 0 else L.T, order="F")
+    # the triangle the flags leave unreferenced holds NaN: neither the solves
+    # nor the FP64 residual may read it
+    A[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
     B = synth.rhs_normal(*((k, nrhs) if side == 0 else (nrhs, k)), key=(16, k, 1))
     for inner in (1, 2):
         X, st = mixed(A, B, inner, side, uplo, trans, diag, alpha=-0.75)
