@@ -210,7 +210,7 @@ int64_t redsea_schedule(int variant, int64_t m, int nb, int64_t* tasks, int64_t 
  * A[i + k*lda] (transa = 0) or A[k + i*lda] (transa = 1).  transx = 0: X is
  * K x N at X[k + j*ldx] and C is M x N at C[i + j*ldc]; transx = 1: both are
  * stored transposed, X[j + k*ldx] and C[j + i*ldc].  tile selects a kernel
- * tile configuration (0 .. 16) or -1 for the default.  Argument numbers:
+ * tile configuration (0 .. 17) or -1 for the default.  Argument numbers:
  * dtype 1, transa 2, transx 3, M 4, N 5, K 6, A 7, lda 8, X 9, ldx 10, C 11,
  * ldc 12, tile 13, stream 14.  Asynchronous on stream.
  */

@@ -649,15 +649,21 @@ typedef Cfg<64, 128, 32, 2, 2, 1> Tile7;   // short M, wide N, deeper k-stage
 typedef Cfg<256, 128, 8, 4, 2, 2> Tile10;  // eight waves, short k-stage
 // 8: short-K 64x64, 9: short-K 32x64; FP64 direct-to-LDS: 11: 256x128 on
 // eight waves, 12: 128x128 on four waves (two workgroups per CU), 13:
-// 128x128 on eight waves, 14: 64x64, 15: 128x64, 16: 64x128 (four waves each)
-constexpr int kTiles = 17;
+// 128x128 on eight waves, 14: 64x64, 15: 128x64, 16: 64x128 (four waves each),
+// 17: 64x32 (four waves of 32x16, for short products with many columns)
+constexpr int kTiles = 18;
 
 // Direct-to-LDS FP64 tiles where the shape allows them, else the register-
 // staged tile of the same size.
+// staging layouts exist for k-major operands of any width that is a multiple
+// of 8 and for m/j-major ones 64 wide or a multiple of 128 wide
+constexpr bool dma_width_ok(int bw, bool kmajor) { return kmajor ? bw % 8 == 0 : (bw == 64 || bw % 128 == 0); }
+
 template <typename T, int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, typename Fallback>
 hipError_t gemm_dma_or(const GemmArgs& g, hipStream_t s) {
-    if (sizeof(T) == 8 && dma_ok<BM, BN, AT, RT>(g))
-        return gemm_dma_launch_f64<BM, BN, WM, WN, MINB, AT, RT>(g, s);
+    if constexpr (sizeof(T) == 8 && dma_width_ok(BM, AT) && dma_width_ok(BN, !RT)) {
+        if (dma_ok<BM, BN, AT, RT>(g)) return gemm_dma_launch_f64<BM, BN, WM, WN, MINB, AT, RT>(g, s);
+    }
     return gemm_launch_t<T, Fallback, AT, RT>(g, s);
 }
 
@@ -681,6 +687,7 @@ hipError_t gemm_by_tile(int tile, const GemmArgs& g, hipStream_t s) {
         case 14: return gemm_dma_or<T, 64, 64, 2, 2, 4, AT, RT, Tile6>(g, s);
         case 15: return gemm_dma_or<T, 128, 64, 2, 2, 2, AT, RT, Tile3>(g, s);
         case 16: return gemm_dma_or<T, 64, 128, 2, 2, 2, AT, RT, Tile4>(g, s);
+        case 17: return gemm_dma_or<T, 64, 32, 2, 2, 4, AT, RT, Tile6>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -748,13 +755,14 @@ int gemm_tile_count() { return kTiles; }
 
 // Default tile for a product shape, from sweeps of the configurations on
 // MI355X (N = 8192).  FP64: the direct-to-LDS 128 x 128 eight-wave tile once
-// M and K reach 1024, the direct-to-LDS 64 x 64 tile below that (each falls
-// back to a register-staged tile on shapes the direct path does not accept).
+// M and K reach 1024, the direct-to-LDS 64 x 64 tile below that and the
+// 64 x 32 tile for M <= 256 (each falls back to a register-staged tile on
+// shapes the direct path does not accept).
 // FP32: the short-K kernel for small square updates, 64 x 64 tiles for short
 // M or K, the eight-wave 256 x 128 tile otherwise.
 int gemm_default_tile(int dtype, int64_t M, int64_t N, int64_t K) {
     (void)N;
-    if (dtype == 0) return (M >= 1024 && K >= 1024) ? 13 : 14;
+    if (dtype == 0) return (M >= 1024 && K >= 1024) ? 13 : (M <= 256 ? 17 : 14);
     if (K <= 160 && M <= 160) return 9;
     if (M <= 768 || K <= 384) return 3;
     return 5;

@@ -13,7 +13,7 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 U64, U32 = 2.0 ** -53, 2.0 ** -24
-TILES = list(range(17))
+TILES = list(range(18))
 
 
 def _run(A, X, C, transa, transx, tile, dtype):
@@ -56,7 +56,7 @@ def test_update_integer_exact(tile, dtype):
 
 @pytest.mark.parametrize("transa,transx", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_direct_lds_tiles_match_register_staged(transa, transx):
-    # Tiles 11-16 stage operands with direct-to-LDS loads; on shapes they
+    # Tiles 11-17 stage operands with direct-to-LDS loads; on shapes they
     # accept they run the same MFMA sequence in the same k order as the
     # register-staged tile 5, so the results agree bit for bit.  Shapes span
     # several tiles with ragged tails in every dimension (all even, as the
@@ -67,7 +67,7 @@ def test_direct_lds_tiles_match_register_staged(transa, transx):
         X = r.standard_normal((K, N))
         C = r.standard_normal((M, N))
         want = _run(A, X, C, transa, transx, 5, np.float64)
-        for fast in range(11, 17):
+        for fast in range(11, 18):
             got = _run(A, X, C, transa, transx, fast, np.float64)
             assert np.array_equal(got, want), (M, N, K, fast)
         ref = C - A @ X
