@@ -406,6 +406,38 @@ struct DmaOp {
         }
         __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 16, voff, 0, 0, 0);
     }
+    // The same chunk in four 4-byte loads per lane (quarter u covers bytes
+    // [256u, 256u + 256) of the chunk; lanes 2i and 2i+1 carry the two halves
+    // of one element).  Each element is checked on its own, so no index has
+    // to be even, and every access is 4-byte aligned whatever ld is.
+    static __device__ __forceinline__ void load_dw(const double* p, int64_t ld, int64_t wlim,
+                                                   int64_t klim, char* lds, int q, int lane) {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)kDmaOob, 0x00020000);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int d = u * 32 + (lane >> 1), half = lane & 1;  // element d of the chunk
+            int k, w;
+            char* dst;
+            if (KMAJOR) {
+                const int t = d >> 1, wl = t >> 3, kp = (t & 7) ^ swz(wl, q);
+                k = 2 * kp + (d & 1);
+                w = 8 * q + wl;
+                dst = lds + q * 1024 + u * 256;
+            } else if (NARROW) {
+                k = 4 * (q >> 1) + (q & 1) + 2 * (d >> 6);
+                w = d & 63;
+                dst = lds + q * 1152 + u * 256;
+            } else {
+                k = q / PER_ROW;
+                w = (q % PER_ROW) * 128 + d;
+                dst = lds + k * ROW * 8 + (q % PER_ROW) * 1024 + u * 256;
+            }
+            const int64_t e = KMAJOR ? k + w * ld : w + k * ld;
+            const unsigned voff = (w < wlim && k < klim) ? (unsigned)(e * 8 + 4 * half) : kDmaOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)dst, 4, voff, 0, 0, 0);
+        }
+    }
     // Element offset (doubles) of (k = 4*ks + lane/16, w = wb + 16*f + lane%16)
     // without the f term: the fragment f adds fstride() elements.
     static __device__ __forceinline__ int frag_off(int ks, int wb, int lane) {
@@ -430,7 +462,7 @@ struct DmaCfg {
     static_assert(SM % 16 == 0 && SN % 16 == 0, "wave tile");
 };
 
-template <typename D, bool AT, bool RT>
+template <typename D, bool AT, bool RT, bool DW>
 __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t n0, int64_t k0,
                                           char* st, int wave, int lane) {
     const double* a = (const double*)g.a;
@@ -439,11 +471,15 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
     const double* px = RT ? x + n0 + k0 * g.ldx : x + k0 + n0 * g.ldx;
     const int64_t mlim = g.M - m0, nlim = g.N - n0, klim = g.K - k0;
 #pragma unroll
-    for (int i = 0; i < D::OA::CHUNKS / D::NW; ++i)
-        D::OA::load(pa, g.lda, mlim, klim, st, i * D::NW + wave, lane);
+    for (int i = 0; i < D::OA::CHUNKS / D::NW; ++i) {
+        if (DW) D::OA::load_dw(pa, g.lda, mlim, klim, st, i * D::NW + wave, lane);
+        else D::OA::load(pa, g.lda, mlim, klim, st, i * D::NW + wave, lane);
+    }
 #pragma unroll
-    for (int i = 0; i < D::OX::CHUNKS / D::NW; ++i)
-        D::OX::load(px, g.ldx, nlim, klim, st + D::OA::BYTES, i * D::NW + wave, lane);
+    for (int i = 0; i < D::OX::CHUNKS / D::NW; ++i) {
+        if (DW) D::OX::load_dw(px, g.ldx, nlim, klim, st + D::OA::BYTES, i * D::NW + wave, lane);
+        else D::OX::load(px, g.ldx, nlim, klim, st + D::OA::BYTES, i * D::NW + wave, lane);
+    }
 }
 
 // TRI = 0: C -= A X.  TRI = 1 / 2: A is the lower / upper triangle of its
@@ -452,7 +488,10 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
 // triangular solve.  Only the k-stages that meet the triangle in rows
 // [m0, m0 + BM) are run, and in the stages that cross the diagonal the A
 // fragments are masked after they are read from LDS.
-template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false>
+// DW: operands loaded with 4-byte lane accesses (any shape, any leading
+// dimension) instead of 16-byte ones (even shapes and leading dimensions).
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false,
+          bool DW = false>
 __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g, double alpha_c) {
     typedef DmaCfg<BM, BN, WM, WN, MINB, AT, RT> D;
     __shared__ __attribute__((aligned(1024))) char smem[2 * D::STAGE];
@@ -502,7 +541,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
         const bool inside = TRI == 1 ? kcol <= m : kcol >= m;
         return inside ? ((UNIT && kcol == m) ? 1.0 : v) : 0.0;
     };
-    if (kb < ke) dma_stage<D, AT, RT>(g, m0, n0, kb * kDmaBk, smem + (kb & 1) * D::STAGE, wave, lane);
+    if (kb < ke) dma_stage<D, AT, RT, DW>(g, m0, n0, kb * kDmaBk, smem + (kb & 1) * D::STAGE, wave, lane);
     __syncthreads();
     double la[D::FM], lx[D::FN];  // fragments of the last k-step, used after the barrier
     for (int64_t kt = kb; kt < ke; ++kt) {
@@ -513,8 +552,8 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
         // a stage crossing the diagonal of this row tile (uniform)
         const bool diag = TRI != 0 && k0 + kDmaBk > m0 && k0 < m0 + BM;
         if (kt + 1 < ke)
-            dma_stage<D, AT, RT>(g, m0, n0, (kt + 1) * kDmaBk, smem + ((kt + 1) & 1) * D::STAGE,
-                                 wave, lane);
+            dma_stage<D, AT, RT, DW>(g, m0, n0, (kt + 1) * kDmaBk, smem + ((kt + 1) & 1) * D::STAGE,
+                                     wave, lane);
         if (kt > kb) {
 #pragma unroll
             for (int i = 0; i < D::FM; ++i)
@@ -574,10 +613,19 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
             }
 }
 
-// Shapes the direct-to-LDS kernel accepts: every index that is loaded in
-// pairs is even, leading dimensions are even and operands 16-byte aligned (so
-// a pair never straddles the end of a row or column), and one stage of each
-// operand spans less than the 2 GB byte-offset range of a buffer load.
+// Shapes the direct-to-LDS kernel accepts.  16-byte loads: every index that
+// is loaded in pairs is even, leading dimensions are even and operands
+// 16-byte aligned (so a pair never straddles the end of a row or column).
+// 4-byte loads: any shape.  Either way one stage of each operand must span
+// less than the 1 GB byte-offset range used for a buffer load.
+template <int BM, int BN, bool AT, bool RT>
+bool dma_span_ok(const GemmArgs& g) {
+    const int64_t lim = (int64_t)1 << 30;
+    const int64_t sa = AT ? (kDmaBk + (BM - 1) * g.lda) * 8 : (BM + (kDmaBk - 1) * g.lda) * 8;
+    const int64_t sx = RT ? (BN + (kDmaBk - 1) * g.ldx) * 8 : (kDmaBk + (BN - 1) * g.ldx) * 8;
+    return sa < lim && sx < lim && (((uintptr_t)g.a | (uintptr_t)g.x) & 3) == 0;
+}
+
 template <int BM, int BN, bool AT, bool RT>
 bool dma_ok(const GemmArgs& g) {
     if ((g.lda | g.ldx) & 1) return false;
@@ -585,16 +633,14 @@ bool dma_ok(const GemmArgs& g) {
     if (g.K & 1) return false;                   // k pairs (A^T or X) and k tails
     if (!AT && (g.M & 1)) return false;          // m pairs
     if (RT && (g.N & 1)) return false;           // j pairs
-    const int64_t lim = (int64_t)1 << 30;
-    const int64_t sa = AT ? (kDmaBk + (BM - 1) * g.lda) * 8 : (BM + (kDmaBk - 1) * g.lda) * 8;
-    const int64_t sx = RT ? (BN + (kDmaBk - 1) * g.ldx) * 8 : (kDmaBk + (BN - 1) * g.ldx) * 8;
-    return sa < lim && sx < lim;
+    return dma_span_ok<BM, BN, AT, RT>(g);
 }
 
-template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false>
+template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false,
+          bool DW = false>
 hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s, double alpha_c = 1.0) {
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT, TRI, UNIT>),
+    hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT, TRI, UNIT, DW>),
                        dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, alpha_c);
     return hipGetLastError();
 }
@@ -663,6 +709,8 @@ template <typename T, int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT
 hipError_t gemm_dma_or(const GemmArgs& g, hipStream_t s) {
     if constexpr (sizeof(T) == 8 && dma_width_ok(BM, AT) && dma_width_ok(BN, !RT)) {
         if (dma_ok<BM, BN, AT, RT>(g)) return gemm_dma_launch_f64<BM, BN, WM, WN, MINB, AT, RT>(g, s);
+        if (dma_span_ok<BM, BN, AT, RT>(g))
+            return gemm_dma_launch_f64<BM, BN, WM, WN, MINB, AT, RT, 0, false, true>(g, s);
     }
     return gemm_launch_t<T, Fallback, AT, RT>(g, s);
 }
@@ -729,6 +777,9 @@ hipError_t residual_u(bool unit, const GemmArgs& g, double alpha, hipStream_t s)
     if (dma_ok<128, 128, AT, RT>(g))
         return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true>(g, s, alpha)
                     : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false>(g, s, alpha);
+    if (dma_span_ok<128, 128, AT, RT>(g))
+        return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true, true>(g, s, alpha)
+                    : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false, true>(g, s, alpha);
     return unit ? residual_launch<Tile5, AT, RT, TRI, true>(g, alpha, s)
                 : residual_launch<Tile5, AT, RT, TRI, false>(g, alpha, s);
 }

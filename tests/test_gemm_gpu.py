@@ -61,7 +61,9 @@ def test_direct_lds_tiles_match_register_staged(transa, transx):
     # register-staged tile 5, so the results agree bit for bit.  Shapes span
     # several tiles with ragged tails in every dimension (all even, as the
     # direct path requires).
-    for (M, N, K) in [(520, 390, 266), (256, 128, 16), (2, 2, 2), (258, 130, 18), (768, 256, 1024)]:
+    # odd shapes take the 4-byte-load variant of the same kernels
+    for (M, N, K) in [(520, 390, 266), (256, 128, 16), (2, 2, 2), (258, 130, 18), (768, 256, 1024),
+                      (521, 391, 267), (37, 129, 5), (255, 131, 17), (1, 1, 1)]:
         r = synth.rng((33, M, N + K))
         A = r.standard_normal((M, K))
         X = r.standard_normal((K, N))
@@ -73,6 +75,38 @@ def test_direct_lds_tiles_match_register_staged(transa, transx):
         ref = C - A @ X
         bound = 2 * K * U64 * (np.abs(C) + np.abs(A) @ np.abs(X))
         assert np.all(np.abs(got - ref) <= bound), (M, N, K)
+
+
+@pytest.mark.parametrize("transa,transx", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_direct_lds_odd_leading_dimensions(transa, transx):
+    # Operands as column blocks of larger arrays with odd leading dimensions
+    # and odd offsets (8-byte aligned only): the direct path loads them with
+    # 4-byte accesses and must still agree bit for bit with tile 5.
+    M, N, K = 300, 200, 150
+    r = synth.rng((34, transa, transx))
+    A = r.standard_normal((M, K))
+    X = r.standard_normal((K, N))
+    C = r.standard_normal((M, N))
+
+    def padded(mat, extra):
+        big = np.full((mat.shape[0] + extra, mat.shape[1] + 1), np.nan, order="F")
+        big[1:1 + mat.shape[0], 1:] = mat
+        t = rs.fortran_tensor(big)
+        return t[1:1 + mat.shape[0], 1:]
+
+    outs = []
+    for tile in (5, 11, 12, 13, 14, 15, 16, 17):
+        dA = padded(A.T if transa else A, 3)
+        dX = padded(X.T if transx else X, 5)
+        dC = padded(C.T if transx else C, 7)
+        rs.gemm_update(dA, dX, dC, transa=transa, transx=transx, tile=tile)
+        torch.cuda.synchronize()
+        out = dC.cpu().numpy()
+        outs.append(out.T if transx else out)
+    for tile, out in zip((11, 12, 13, 14, 15, 16, 17), outs[1:]):
+        assert np.array_equal(out, outs[0]), tile
+    ref = C - A @ X
+    assert np.all(np.abs(outs[0] - ref) <= 2 * K * U64 * (np.abs(C) + np.abs(A) @ np.abs(X)))
 
 
 def test_update_fp32_bound():
