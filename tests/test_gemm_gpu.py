@@ -135,3 +135,18 @@ def test_update_leaves_outside_untouched():
     torch.cuda.synchronize()
     out = dC.cpu().numpy()
     assert np.all(out[M:] == 9.0)
+
+
+def test_mfma_peak_probe():
+    # The diagnostic MFMA-only probe reports a positive operation count and a
+    # rate in the range of the matrix cores (FP32 about twice FP64); bad
+    # arguments are rejected before any launch.
+    L = rs.lib()
+    out = torch.empty(4096 * 256, dtype=torch.float64, device="cuda")
+    assert L.redsea_mfma_peak(0, 0, out.data_ptr(), out.numel(), None) == -1
+    assert L.redsea_mfma_peak(7, 16, out.data_ptr(), out.numel(), None) == -1
+    assert L.redsea_mfma_peak(0, 16, out.data_ptr(), 100, None) == -3
+    f64 = rs.mfma_peak("f64", iters=512, reps=3)
+    f32 = rs.mfma_peak("f32", iters=512, reps=3)
+    assert 10.0 < f64 < 100.0, f64
+    assert f32 > 1.5 * f64, (f32, f64)

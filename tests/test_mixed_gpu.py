@@ -80,6 +80,21 @@ def test_all_flags_backward_error(side, uplo, trans, diag):
         assert eta <= 1e-12, (inner, eta, st.iterations, st.fell_back)
 
 
+@pytest.mark.parametrize("side,uplo,trans,diag", [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 1, 1), (1, 1, 0, 0)])
+def test_odd_sizes_backward_error(side, uplo, trans, diag):
+    # odd order and right-hand-side count: the FP64 residual runs on the
+    # 4-byte-load variant of the product kernel in triangle mode
+    k, nrhs = 401, 37
+    L = synth.unit_lower(k, (20, k, 0)) if diag else synth.dominant_lower(k, (20, k, 0))
+    A = np.array(L if uplo == 0 else L.T, order="F")
+    A[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    B = synth.rhs_normal(*((k, nrhs) if side == 0 else (nrhs, k)), key=(20, k, 1))
+    for inner in (1, 2):
+        X, st = mixed(A, B, inner, side, uplo, trans, diag, alpha=1.5)
+        eta = oracle.backward_error(side, uplo, trans, diag, 1.5, A, B, X)
+        assert eta <= 1e-12, (inner, eta, st.iterations, st.fell_back)
+
+
 def test_unreachable_tolerance_falls_back_to_fp64():
     n, nrhs = 700, 20
     L = synth.dominant_lower(n, (17, 0, 0))
