@@ -27,10 +27,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2305_19917_amd", "csrc", "k_gemm.hip")
 
 
-def measured_traffic():
+def measured_traffic(n, nrhs, variant, nb):
     """HBM bytes per product launch from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None when
-    the product kernel's source changed since they were taken."""
+    they were taken on another workload or the product kernel's source
+    changed since."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -39,12 +40,21 @@ def measured_traffic():
         return None
     if rec.get("kernel_source_sha256") != sha:
         return None
+    if (rec.get("n"), rec.get("nrhs"), rec.get("variant"), rec.get("nb")) != (n, nrhs, variant, nb):
+        return None
     return rec.get("bytes_per_launch")
+
+
+def leaf_rows(nb):
+    """Rows of the leaf kernel for leaf size nb (the library splits larger
+    leaves recursively down to 256 rows)."""
+    return 256 if nb >= 256 else min(nb, 128)
 
 
 def algorithmic_bytes(n, nrhs, nb):
     """8 (MK + KN + 2MN) summed over the product launches of the recursive
     schedule down to leaves of nb rows, per launch (the unit of `traffic`)."""
+    nb = leaf_rows(nb)
     total, count = 0, 0
     def split(rows):
         nonlocal total, count
@@ -93,7 +103,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--nrhs", type=int, default=8192)
     ap.add_argument("--variant", default="recursive")
-    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -207,7 +217,8 @@ def main():
         "eta_sampled": eta,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK, 4),
-                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                     "traffic": measured_traffic(n, nrhs, args.variant, args.nb),
+                     "traffic_unit": "bytes per launch",
                      "algorithmic_bytes_per_launch": (round(algorithmic_bytes(n, nrhs, args.nb))
                                                       if args.variant == "recursive" else None),
                      "kernel": "gemm_dma_kernel (FP64 product update, all tiles)",

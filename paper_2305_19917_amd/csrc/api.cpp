@@ -335,8 +335,16 @@ int column_groups(const Canon& c) {
     return g;
 }
 
+// Rows of the leaf kernel's block for leaf size nb: up to 128 rows one wave
+// per 16 columns holds the whole block; 256 rows are solved by the segmented
+// leaf (two 128-row segments, the split between them inside the kernel).
+// Larger leaves are split recursively down to 256 rows: a segmented leaf of
+// four segments needs two waves per SIMD, where its FP64 matrix and vector
+// work contend, and measured slower than two 256-row leaves and a product.
+static int64_t leaf_rows(int64_t nb) { return nb >= 256 ? 256 : std::min<int64_t>(nb, 128); }
+
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
-    const int64_t kleaf = std::min<int64_t>(nb, 128);
+    const int64_t kleaf = leaf_rows(nb);
     const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
     const int64_t nblk = (c.k + kleaf - 1) / kleaf;
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;

@@ -28,7 +28,8 @@ hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int6
                             int64_t nblk, bool unit, void* packed, hipStream_t s);
 
 // Solves the leaf at rows [row0, row0+rows) for all ncols columns, reading the
-// packed diagonal block `pblk` (nb x nb).  unit: skip the division.
+// packed diagonal block `pblk` (nb x nb, nb one of 16, 32, 64, 128, 256;
+// rows <= nb).  unit: skip the division.
 hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const RhsView& B,
                        int64_t row0, int64_t ncols, bool unit, hipStream_t s);
 

@@ -54,7 +54,7 @@ def _shape(side, k, nrhs):
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("nb", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("nb", [16, 32, 64, 128, 256, 512])
 def test_config0_all_variants(variant, nb):
     n, nrhs = 512, 64
     _say("config0", variant, nb)
@@ -70,13 +70,33 @@ def test_config0_all_variants(variant, nb):
 @pytest.mark.parametrize("side,uplo,trans,diag", FLAGS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_integer_exact_all_flags(side, uplo, trans, diag, dtype):
-    for k, nrhs, nb in [(37, 5, 16), (200, 70, 64), (300, 33, 128)]:
+    for k, nrhs, nb in [(37, 5, 16), (200, 70, 64), (300, 33, 128), (300, 9, 256), (429, 20, 512)]:
         m, n = _shape(side, k, nrhs)
         _say("intexact", side, uplo, trans, diag, k, nrhs, nb, dtype.__name__)
         A, B, Xt = synth.integer_exact(m, n, (5, k, nrhs), side, uplo, trans, diag)
         for variant in VARIANTS:
             X = gpu_solve(A, B, side, uplo, trans, diag, variant=variant, nb=nb, dtype=dtype)
             assert np.array_equal(X, Xt), (variant, k, nrhs)
+
+
+@pytest.mark.parametrize("nb", [256, 512])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_segmented_leaf_ragged(nb, dtype):
+    """Leaves of 256 rows run the segmented leaf kernel (two 128-row
+    segments, one wave each); nb = 512 splits its blocks into such leaves.
+    The orders leave one or both segments of a leaf occupied, with ragged
+    segments, and span several leaves; the column counts leave partial
+    column groups."""
+    bar = 1e-14 if dtype == np.float64 else 5e-6
+    for k, nrhs in [(100, 45), (300, 17), (429, 33), (512, 64), (700, 1), (1100, 70)]:
+        _say("segmented", nb, dtype.__name__, k, nrhs)
+        L = synth.dominant_lower(k, (15, k, 0)).astype(dtype)
+        B = synth.rhs_normal(k, nrhs, (15, k, 1)).astype(dtype)
+        for variant in VARIANTS:
+            X = gpu_solve(L, B, variant=variant, nb=nb, dtype=dtype)
+            eta = oracle.backward_error(0, 0, 0, 0, 1.0, L.astype(np.float64),
+                                        B.astype(np.float64), X)
+            assert eta <= bar * k, (k, nrhs, variant, eta)
 
 
 @pytest.mark.parametrize("side,uplo,trans,diag", FLAGS)
