@@ -336,11 +336,11 @@ int column_groups(const Canon& c) {
 }
 
 // Rows of the leaf kernel's block for leaf size nb: up to 128 rows one wave
-// per 16 columns holds the whole block; 256 rows are solved by the segmented
-// leaf (two 128-row segments, the split between them inside the kernel).
-// Larger leaves are split recursively down to 256 rows: a segmented leaf of
-// four segments needs two waves per SIMD, where its FP64 matrix and vector
-// work contend, and measured slower than two 256-row leaves and a product.
+// per 16 columns holds the whole block; 256 rows are solved by two waves per
+// 16 columns holding alternate 16-row blocks (leaf_ilv_kernel).  Larger
+// leaves are split recursively down to 256 rows: more waves per column group
+// put two waves on a SIMD, where the FP64 matrix work of one and the FP64
+// substitution of the other contend, and measured slower.
 static int64_t leaf_rows(int64_t nb) { return nb >= 256 ? 256 : std::min<int64_t>(nb, 128); }
 
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {

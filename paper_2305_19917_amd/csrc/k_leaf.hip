@@ -187,154 +187,150 @@ hipError_t leaf_mfma_dispatch(const TS* P, int64_t rows, TS* B, int64_t off, int
     return hipGetLastError();
 }
 
-// Elements e = e0 + x + k*NS (k < PER) of the lower triangle of segment t of
-// a packed NP2 x NP2 diagonal block, copied by thread x of NS into dst in the
-// blocked LDS layout of leaf_mfma_kernel: 16 x 16 block (p, s) of the segment
-// is block (8t + p, 8t + s) of the square; diagonal blocks first, then
-// p > s at 8 + p(p-1)/2 + s; element (row j, column i) at [i*16 + j].
-template <typename TS, int NP2, int PER, int NS>
-__device__ __forceinline__ void stage_tri(const TS* __restrict__ P, int t, double* dst, int e0,
-                                          int x) {
-    const TS* Pt = P + (int64_t)128 * t * NP2 + 128 * t;
-    double v[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = e0 + x + k * NS, blk = e >> 8, i = (e >> 4) & 15, j = e & 15;
-        int pp = blk, ss = blk;
-        if (blk >= 8) {
-            int u = blk - 8;
-            pp = 1;
-            while (u >= pp) {
-                u -= pp;
-                ++pp;
-            }
-            ss = u;
-        }
-        v[k] = (double)Pt[(16 * ss + i) * NP2 + 16 * pp + j];
-    }
-#pragma unroll
-    for (int k = 0; k < PER; ++k) dst[e0 + x + k * NS] = v[k];
-}
-
-// Segmented leaf: a diagonal block of NQ*128 rows solved in one launch.  A
-// workgroup covers CG column groups of 16 right-hand sides; each column group
-// has NQ waves, wave q holding rows [128q, 128q + 128) of its 16 columns in
-// accumulator layout (as in leaf_mfma_kernel).  The block is the recursive
-// split of Sec. V-A carried out inside the kernel: in phase t, wave t solves
-// its segment against the segment's triangle (in LDS) exactly as
-// leaf_mfma_kernel does, and publishes every solved 16-row block through LDS;
-// each later wave of the column group applies that block to its own rows at
-// once on the matrix cores (the off-diagonal product of the split), reading
-// the coupling block from the packed diagonal block in global memory, where
-// all workgroups share it in L2.  When phase t ends, segment t+1 has received
-// all of its updates; no product between segments goes through HBM.  The
-// triangle of segment t+1 is staged into the second LDS buffer by the waves
-// of segment t+1 during phase t, one slice per 16-row step, so no phase waits
-// for its triangle.
-template <typename TS, int NQ, int CG, bool UNIT, bool FULL>
-__global__ __launch_bounds__(64 * NQ * CG) void leaf_seg_kernel(const TS* __restrict__ P, int rows,
-                                                                TS* __restrict__ B, int64_t off,
-                                                                int64_t br, int64_t bc,
-                                                                int64_t ncols) {
-    constexpr int NP2 = 128 * NQ;          // order of the packed block
-    constexpr int NF = 8, NO = 28;         // 16-row blocks of a segment
-    constexpr int NT = 64 * NQ * CG;       // threads
-    constexpr int NE = (NF + NO) * 256;    // triangle elements of a segment
-    constexpr int SL = NE / NF;            // elements staged per 16-row step
-    static_assert(NE % NT == 0 && SL % (64 * CG) == 0, "staging assumes whole passes");
-    __shared__ double Ls[2][NE];           // triangles of phases t (t & 1)
+// Interleaved 256-row leaf.  Each column group of 16 right-hand sides has two
+// waves; wave v holds the 16-row blocks s = v, v + 2, ..., 14 + v of the leaf
+// (fragment j is block 2j + v, accumulator layout as in leaf_mfma_kernel).
+// Block s is solved by its owner wave, which publishes the solution x_s
+// through LDS.  After the block barrier the other wave, owner of block
+// s + 1, applies x_s to that block only (four MFMAs on the critical path)
+// and goes on to solve it; x_s reaches its later blocks one step after, in
+// the same order.  The owner of block s meanwhile applies x_{s-1} and x_s to
+// its own later blocks.  Every update is the Sec. IV product of a solved
+// block into the rows below, applied block by block in increasing s; the
+// coupling blocks are read from the packed diagonal block (in L2) while the
+// owner substitutes.  Only the 16 diagonal 16 x 16 blocks live in LDS.
+template <typename TS, int CG, bool UNIT, bool FULL>
+__global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict__ P, int rows,
+                                                            TS* __restrict__ B, int64_t off,
+                                                            int64_t br, int64_t bc,
+                                                            int64_t ncols) {
+    constexpr int NP2 = 256, NBK = 16, NJ = 8, NT = 128 * CG;
+    static_assert((NBK * 256) % NT == 0, "staging assumes whole passes");
+    __shared__ double Ds[NBK * 256];       // diagonal block s at s*256, [i*16 + j]
     __shared__ double Xs[CG][16][17];      // gather buffer of the solving wave
     __shared__ v4d Xb[2][CG][64];          // solved blocks, accumulator layout
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
-    const int q = w / CG, cg = w % CG;
-    const int nseg = FULL ? NQ : (rows + 127) / 128;
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar branches
+    const int v = w / CG, cg = w % CG;
     const int64_t col = (int64_t)blockIdx.x * (16 * CG) + cg * 16 + c;
     const bool colok = col < ncols;
     TS* bp = B + off + (colok ? col : 0) * bc;
-    v4d fr[NF];
+    v4d fr[NJ];
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = 128 * q + 16 * f + g + 4 * r;
-            fr[f][r] = (colok && (FULL || row < rows)) ? (double)bp[row * br] : 0.0;
+            const int row = 16 * (2 * j + v) + g + 4 * r;
+            fr[j][r] = (colok && (FULL || row < rows)) ? (double)bp[row * br] : 0.0;
         }
-    stage_tri<TS, NP2, NE / NT, NT>(P, 0, Ls[0], 0, tid);
+    {
+        double t[NBK * 256 / NT];
+#pragma unroll
+        for (int k = 0; k < NBK * 256 / NT; ++k) {
+            const int e = tid + k * NT, b = e >> 8, i = (e >> 4) & 15, jj = e & 15;
+            t[k] = (double)P[(16 * b + i) * NP2 + 16 * b + jj];
+        }
+#pragma unroll
+        for (int k = 0; k < NBK * 256 / NT; ++k) Ds[tid + k * NT] = t[k];
+    }
     __syncthreads();
-    for (int t = 0; t < nseg; ++t) {
-        // Ls[t & 1] was completed before the last block barrier of phase t-1,
-        // and nobody reads Ls[(t + 1) & 1] after that barrier
-        const double* Lt = Ls[t & 1];
-        const bool solver = q == t, later = q > t && q < nseg;
-        const bool stager = q == t + 1 && q < nseg;
+    // A operand of k-slice kk for block (p, s): element (16p + c, 16s + 4kk + g)
+    auto lop = [&](int p, int s, int kk) -> double {
+        return -(double)P[(16 * s + 4 * kk + g) * NP2 + 16 * p + c];
+    };
+    // Coupling blocks the owner of block s applies right after solving it:
+    // (p, s - 1) and (p, s) for its blocks p = 2j + (s & 1) > s.  Loaded two
+    // steps ahead into the other half of a double buffer (the owner's steps
+    // alternate halves), right after the previous barrier.
+    double adq[2][NJ][2][4];
+    auto load_deferred = [&](int s) {
 #pragma unroll
-        for (int s = 0; s < NF; ++s) {
-            const int b = NF * t + s;  // block column in the packed square
-            double a[NF][4];           // coupling block (L_qb), later waves only
-            if (solver) {
-                solve_diag16<UNIT>(Lt + s * 256, Xs[cg], fr[s], g, c);
-                Xb[b & 1][cg][lane] = fr[s];
-            } else if (later) {
-                // A operand of k-slice kk for fragment p: element
-                // (128q + 16p + c, 16b + 4kk + g) of the square, loaded while
-                // block b is being solved
-                const TS* Pc = P + (int64_t)(16 * b + g) * NP2 + 128 * q + c;
+        for (int j = (s >> 1) + 1; j < NJ; ++j)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                if (s > 0) adq[(s >> 1) & 1][j][0][kk] = lop(2 * j + (s & 1), s - 1, kk);
+                adq[(s >> 1) & 1][j][1][kk] = lop(2 * j + (s & 1), s, kk);
+            }
+    };
+    double ac[4];  // block (s + 1, s), applied by the owner of block s + 1
+    auto load_critical = [&](int s) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) ac[kk] = lop(s + 1, s, kk);
+    };
+    if (v == 0) {
+        load_deferred(0);
+    } else {
+        load_critical(0);
+        load_deferred(1);
+    }
+    v4d xp = {0.0, 0.0, 0.0, 0.0};  // x_{s-1}, not yet applied to the later own blocks
+#pragma clang loop unroll(full)
+    for (int s = 0; s < NBK; ++s) {
+        const int par = s & 1, jo = s >> 1;  // owner parity, owner's fragment
+        const bool own = v == par;
+        if (own) {
+            solve_diag16<UNIT>(Ds + s * 256, Xs[cg], fr[jo], g, c);
+            Xb[par][cg][lane] = fr[jo];
+        }
+        __syncthreads();  // x_s published
+        if (own) {
+            // operands of this wave's next two steps: the critical update of
+            // step s + 1 and the deferred updates of step s + 2
+            if (s + 2 < NBK) {
+                load_critical(s + 1);
+                load_deferred(s + 2);
+            }
+            double (&ad)[NJ][2][4] = adq[(s >> 1) & 1];
+            if (s > 0) {
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-                    for (int p = 0; p < NF; ++p) a[p][kk] = -(double)Pc[4 * kk * NP2 + 16 * p];
-                if (stager)
-                    stage_tri<TS, NP2, SL / (64 * CG), 64 * CG>(P, t + 1, Ls[(t + 1) & 1],
-                                                                 s * SL, cg * 64 + lane);
+                    for (int j = jo + 1; j < NJ; ++j)
+                        fr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[j][0][kk], xp[kk], fr[j],
+                                                                     0, 0, 0);
             }
-            __syncthreads();  // block b published
-            if (solver) {
 #pragma unroll
-                for (int p = s + 1; p < NF; ++p) {
-                    const double* Lo = Lt + (NF + p * (p - 1) / 2 + s) * 256;
+            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lo[(4 * kk + g) * 16 + c],
-                                                                     fr[s][kk], fr[p], 0, 0, 0);
-                }
-            } else if (later) {
-                const v4d xb = Xb[b & 1][cg][lane];
+                for (int j = jo + 1; j < NJ; ++j)
+                    fr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[j][1][kk], fr[jo][kk], fr[j],
+                                                                 0, 0, 0);
+        } else if (s + 1 < NBK) {
+            const v4d xb = Xb[par][cg][lane];
+            const int jn = (s + 1) >> 1;
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
+            for (int kk = 0; kk < 4; ++kk)
+                fr[jn] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], xb[kk], fr[jn], 0, 0, 0);
+            xp = xb;
+        }
+    }
+    if (colok) {
 #pragma unroll
-                    for (int p = 0; p < NF; ++p)
-                        fr[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p][kk], xb[kk], fr[p], 0, 0,
-                                                                     0);
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * (2 * j + v) + g + 4 * r;
+                if (FULL || row < rows) bp[row * br] = (TS)fr[j][r];
             }
-        }
-        if (solver && colok) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 128 * q + 16 * f + g + 4 * r;
-                    if (FULL || row < rows) bp[row * br] = (TS)fr[f][r];
-                }
-        }
     }
 }
 
-template <typename TS, int NQ, int CG>
-hipError_t leaf_seg_dispatch(const TS* P, int64_t rows, TS* B, int64_t off, int64_t br, int64_t bc,
+template <typename TS, int CG>
+hipError_t leaf_ilv_dispatch(const TS* P, int64_t rows, TS* B, int64_t off, int64_t br, int64_t bc,
                              int64_t ncols, bool unit, hipStream_t s) {
-    dim3 grid((unsigned)((ncols + 16 * CG - 1) / (16 * CG))), block(64 * NQ * CG);
-    const bool full = rows == 128 * NQ;
+    dim3 grid((unsigned)((ncols + 16 * CG - 1) / (16 * CG))), block(128 * CG);
+    const bool full = rows == 256;
     if (unit && full)
-        hipLaunchKernelGGL((leaf_seg_kernel<TS, NQ, CG, true, true>), grid, block, 0, s, P,
-                           (int)rows, B, off, br, bc, ncols);
+        hipLaunchKernelGGL((leaf_ilv_kernel<TS, CG, true, true>), grid, block, 0, s, P, (int)rows,
+                           B, off, br, bc, ncols);
     else if (unit)
-        hipLaunchKernelGGL((leaf_seg_kernel<TS, NQ, CG, true, false>), grid, block, 0, s, P,
-                           (int)rows, B, off, br, bc, ncols);
+        hipLaunchKernelGGL((leaf_ilv_kernel<TS, CG, true, false>), grid, block, 0, s, P, (int)rows,
+                           B, off, br, bc, ncols);
     else if (full)
-        hipLaunchKernelGGL((leaf_seg_kernel<TS, NQ, CG, false, true>), grid, block, 0, s, P,
-                           (int)rows, B, off, br, bc, ncols);
+        hipLaunchKernelGGL((leaf_ilv_kernel<TS, CG, false, true>), grid, block, 0, s, P, (int)rows,
+                           B, off, br, bc, ncols);
     else
-        hipLaunchKernelGGL((leaf_seg_kernel<TS, NQ, CG, false, false>), grid, block, 0, s, P,
+        hipLaunchKernelGGL((leaf_ilv_kernel<TS, CG, false, false>), grid, block, 0, s, P,
                            (int)rows, B, off, br, bc, ncols);
     return hipGetLastError();
 }
@@ -401,7 +397,7 @@ hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const 
             case 128:
                 return leaf_mfma_dispatch<double, 128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             case 256:
-                return leaf_seg_dispatch<double, 2, 2>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+                return leaf_ilv_dispatch<double, 2>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             default: return hipErrorInvalidValue;
         }
     } else {
@@ -414,7 +410,7 @@ hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const 
             case 128:
                 return leaf_mfma_dispatch<float, 128>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             case 256:
-                return leaf_seg_dispatch<float, 2, 2>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
+                return leaf_ilv_dispatch<float, 2>(P, rows, b, off, B.br, B.bc, ncols, unit, s);
             default: return hipErrorInvalidValue;
         }
     }

@@ -81,15 +81,15 @@ def test_integer_exact_all_flags(side, uplo, trans, diag, dtype):
 
 @pytest.mark.parametrize("nb", [256, 512])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_segmented_leaf_ragged(nb, dtype):
-    """Leaves of 256 rows run the segmented leaf kernel (two 128-row
-    segments, one wave each); nb = 512 splits its blocks into such leaves.
-    The orders leave one or both segments of a leaf occupied, with ragged
-    segments, and span several leaves; the column counts leave partial
-    column groups."""
+def test_two_wave_leaf_ragged(nb, dtype):
+    """Leaves of 256 rows run the two-wave leaf kernel (alternate 16-row
+    blocks per wave); nb = 512 splits its blocks into such leaves.  The
+    orders leave a leaf partly occupied (one wave's blocks only, ragged last
+    block) and span several leaves; the column counts leave partial column
+    groups."""
     bar = 1e-14 if dtype == np.float64 else 5e-6
     for k, nrhs in [(100, 45), (300, 17), (429, 33), (512, 64), (700, 1), (1100, 70)]:
-        _say("segmented", nb, dtype.__name__, k, nrhs)
+        _say("two-wave leaf", nb, dtype.__name__, k, nrhs)
         L = synth.dominant_lower(k, (15, k, 0)).astype(dtype)
         B = synth.rhs_normal(k, nrhs, (15, k, 1)).astype(dtype)
         for variant in VARIANTS:
