@@ -124,7 +124,7 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     double* h_row = host + 3 * nrhs;
 
     const int variant = opts && opts->variant ? opts->variant : VAR_RECURSIVE;
-    const int nb = opts && opts->nb ? opts->nb : 128;
+    const int nb = opts && opts->nb ? opts->nb : 256;
     const bool m_lower = !c64.reverse;
 
     // low-precision copies of the triangle, FP64 copy of B, norms of op(A), alpha B
@@ -190,7 +190,7 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
         // FP64 solve from the kept copy of B
         HIPCHK(launch_copy_scaled(b0, m, m, n, alpha, B, ldb, s));
         Canon c = canonicalize(REDSEA_F64, side, uplo, trans, diag, m, n, A, lda, B, ldb);
-        if ((rc = execute(c, variant, std::min(nb, 128), s))) return rc;
+        if ((rc = execute(c, variant, nb, s))) return rc;
     }
     if (stats) {
         stats->iterations = iters;

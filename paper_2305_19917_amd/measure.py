@@ -106,7 +106,7 @@ def row_thin():
         B = synth.rhs_normal(n, nrhs, (1, 0, 1))
         dB0 = rs.fortran_tensor(B)
         dB = dB0.t().clone().t()
-        ms = _time(lambda: rs.trsm(A, dB, *side_args, variant="recursive", nb=128),
+        ms = _time(lambda: rs.trsm(A, dB, *side_args, variant="recursive", nb=256),
                    lambda: dB.copy_(dB0), reps)
         flops = float(n) * n * nrhs
         byts = 8.0 * (n * (n + 1) / 2 + 2.0 * n * nrhs)
@@ -139,7 +139,7 @@ def row_mixed():
         dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
         dB = dB0.t().clone().t()
         rec = {"row": "mixed", "n": n, "nrhs": nrhs, "kappa_target": e["target"], "kappa1": e["kappa1"]}
-        for name, fn in (("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=128)),
+        for name, fn in (("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=256)),
                          ("fp32_ir", lambda: rs.trsm_mixed(dL, dB, inner=1)),
                          ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2))):
             ms = _time(fn, lambda: dB.copy_(dB0), 3)
