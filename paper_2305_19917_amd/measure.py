@@ -88,7 +88,8 @@ def row_small():
     dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
     dB = dB0.t().clone().t()
     out = {"row": "small", "n": n, "nrhs": nrhs}
-    for variant, nb in (("recursive", 64), ("recursive", 128), ("iterative", 128), ("blocked", 64)):
+    for variant, nb in (("recursive", 64), ("recursive", 128), ("recursive", 256),
+                        ("iterative", 128), ("iterative", 256), ("blocked", 64)):
         ms = _time(lambda: rs.trsm(dL, dB, variant=variant, nb=nb), lambda: dB.copy_(dB0), 200)
         out["%s_nb%d_us" % (variant, nb)] = round(ms * 1e3, 2)
     _emit(out)
