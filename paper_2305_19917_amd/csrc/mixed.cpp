@@ -124,7 +124,7 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     double* h_row = host + 3 * nrhs;
 
     const int variant = opts && opts->variant ? opts->variant : VAR_RECURSIVE;
-    const int nb = opts && opts->nb ? opts->nb : 256;
+    const int nb = pick_nb(opts ? opts->nb : 0, k);
     const bool m_lower = !c64.reverse;
 
     // low-precision copies of the triangle, FP64 copy of B, norms of op(A), alpha B

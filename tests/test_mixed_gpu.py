@@ -102,10 +102,10 @@ def test_unreachable_tolerance_falls_back_to_fp64():
     X, st = mixed(L, B, 2, tol=1e-300, max_iter=3)
     assert st.fell_back == 1
     assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * n
-    # the fallback equals the plain FP64 library solve (the mixed call's
-    # default schedule: recursive, nb 256) bitwise
+    # the fallback equals the plain FP64 library solve with the mixed call's
+    # default schedule (recursive; nb 128 below order 1024) bitwise
     dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
-    rs.trsm(dL, dB, variant="recursive", nb=256)
+    rs.trsm(dL, dB, variant="recursive", nb=128)
     torch.cuda.synchronize()
     assert np.array_equal(X, dB.cpu().numpy())
 
