@@ -82,7 +82,7 @@ typedef enum {
  * informs the automatic choice, never the arithmetic.  When variant, nb and
  * precision are all AUTO the learned picker chooses them (see
  * redsea_pick); an AUTO nb beside a fixed variant or precision is 256 for
- * order(A) >= 1024, else 128. */
+ * order(A) > 128, else 128. */
 typedef struct {
     int variant;   /* redsea_variant   */
     int nb;        /* leaf size or 0   */

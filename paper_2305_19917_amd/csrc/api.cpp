@@ -439,11 +439,12 @@ int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, in
 }
 
 // Leaf size when the caller fixes the variant but not nb: the 256-row leaf
-// from order 1024 up (n = 8192: 56.7 TFLOP/s against 53.3 at nb 128), else
-// 128 (n = 512: 132.7 us against 154.2 at nb 64).
+// above order 128 (n = 8192: 56.7 TFLOP/s against 53.3 at nb 128; n = 512:
+// 97.4 us against 132.6), else 128 (the 256-row kernel always runs its 16
+// block steps).
 int pick_nb(int requested, int64_t k) {
     if (requested > 0) return requested;
-    return k >= 1024 ? 256 : 128;
+    return k > 128 ? 256 : 128;
 }
 
 }  // namespace redsea

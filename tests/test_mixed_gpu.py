@@ -103,9 +103,9 @@ def test_unreachable_tolerance_falls_back_to_fp64():
     assert st.fell_back == 1
     assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * n
     # the fallback equals the plain FP64 library solve with the mixed call's
-    # default schedule (recursive; nb 128 below order 1024) bitwise
+    # default schedule (recursive; nb 256 above order 128) bitwise
     dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
-    rs.trsm(dL, dB, variant="recursive", nb=128)
+    rs.trsm(dL, dB, variant="recursive", nb=256)
     torch.cuda.synchronize()
     assert np.array_equal(X, dB.cpu().numpy())
 
