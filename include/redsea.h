@@ -295,9 +295,11 @@ int redsea_mlp_adam(float* params, const float* grad, float* m, float* v, int64_
  * Picker decision for a solve (HOST call, no device work): the candidate
  * index the library would use for a left solve of order n with nrhs
  * right-hand sides, data type dtype and condition estimate kappa (<= 0:
- * unknown), or -1 when no trained weights are loaded.  *confident is set to
- * 1 when the prediction is inside the training range and the best two
- * predictions differ by more than 5 %.  Weights come from the file named by
+ * unknown), or -1 when no trained weights are loaded.  Outside the range of
+ * orders and widths the network was trained on it is not consulted and the
+ * default schedule is returned (recursive, native precision, nb 256 above
+ * order 128, else 128).  *confident is set to 1 when the shape is inside
+ * the training range and the best two predictions differ by more than 5 %.  Weights come from the file named by
  * REDSEA_MLP_WEIGHTS, else picker_weights.txt next to the library;
  * redsea_mlp_load(path) loads a file explicitly (returns 0 or -1).
  */

@@ -107,6 +107,16 @@ int pick_candidate(int dtype, int64_t n, int64_t nrhs, double kappa, int* confid
     if (!g_net.loaded) return -1;
     const double ln = std::log2((double)std::max<int64_t>(n, 1));
     const double lr = std::log2((double)std::max<int64_t>(nrhs, 1));
+    if (ln < g_net.lo[0] || ln > g_net.hi[0] || lr < g_net.lo[1] || lr > g_net.hi[1]) {
+        // Outside the trained shapes the network is not consulted: the
+        // library's default schedule (recursive, native precision, leaf size
+        // by order) is taken, the measured best at n = nrhs = 8192, where
+        // the network's extrapolation lost 6 %.
+        const int nb = pick_nb(0, n);
+        int idx = 0;
+        while (idx < 4 && kNbs[idx] != nb) ++idx;
+        return 3 * idx;
+    }
     const double lk = std::log10(kappa > 1.0 ? kappa : 1.0);
     const double raw[5] = {ln, lr, (double)dtype, lk, 0.0};
     float x[5];
@@ -124,10 +134,8 @@ int pick_candidate(int dtype, int64_t n, int64_t nrhs, double kappa, int* confid
         }
     }
     if (confident) {
-        const bool in_range = ln >= g_net.lo[0] && ln <= g_net.hi[0] && lr >= g_net.lo[1] &&
-                              lr <= g_net.hi[1];
         const bool separated = second < 0 || (y[second] - y[best]) > std::log(1.05);
-        *confident = in_range && separated ? 1 : 0;
+        *confident = separated ? 1 : 0;
     }
     return best;
 }

@@ -93,3 +93,21 @@ def test_schedule_argument_errors():
     assert L.redsea_schedule(1, 10, 0, None, 0) == -3
     assert L.redsea_schedule(1, 10, 16, None, 5) == -4
     assert L.redsea_schedule(1, 0, 16, None, 0) == 0
+
+
+def test_picker_outside_trained_shapes_takes_default_schedule():
+    """Outside the orders and widths the network was trained on, the host
+    picker returns the default schedule (recursive, native precision, nb 256
+    above order 128, else 128) and reports no confidence; inside, it returns
+    a valid candidate."""
+    L = rs.lib()
+    conf = ctypes.c_int(7)
+    var, nb, prec = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    for dtype, n, nrhs, want_nb in [(0, 16384, 16384, 256), (1, 8192, 8192, 256),
+                                    (0, 100, 100000, 128), (0, 32, 4, 128)]:
+        c = L.redsea_pick(dtype, n, nrhs, 0.0, ctypes.byref(conf))
+        assert conf.value == 0
+        assert L.redsea_candidate(c, ctypes.byref(var), ctypes.byref(nb), ctypes.byref(prec)) == 0
+        assert (var.value, nb.value, prec.value) == (1, want_nb, 1), (n, nrhs, c)
+    c = L.redsea_pick(0, 2000, 300, 9000.0, ctypes.byref(conf))
+    assert 0 <= c < 45
