@@ -5,9 +5,12 @@
 // same tasks appear in Sec. V-B and V-C).  Here it runs on the GPU, by the
 // forward substitution of Sec. IV in axpy order (after unknown k is divided
 // out, every later row is updated with it), on a packed canonical copy of the
-// diagonal block staged in LDS.  FP32 data is solved by the same kernel: it
-// is widened to FP64 on load and rounded to FP32 on store, so an FP32 leaf is
-// at least as accurate as one computed in FP32.
+// diagonal block.  Leaves of up to 128 rows keep the block's whole triangle
+// in LDS (leaf_mfma_kernel); 256-row leaves keep only its 16 x 16 diagonal
+// blocks there and apply the rest as matrix-core products between two waves
+// (leaf_ilv_kernel).  FP32 data is solved by the same kernels: it is widened
+// to FP64 on load and rounded to FP32 on store, so an FP32 leaf is at least
+// as accurate as one computed in FP32.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -196,9 +199,12 @@ hipError_t leaf_mfma_dispatch(const TS* P, int64_t rows, TS* B, int64_t off, int
 // and goes on to solve it; x_s reaches its later blocks one step after, in
 // the same order.  The owner of block s meanwhile applies x_{s-1} and x_s to
 // its own later blocks.  Every update is the Sec. IV product of a solved
-// block into the rows below, applied block by block in increasing s; the
-// coupling blocks are read from the packed diagonal block (in L2) while the
-// owner substitutes.  Only the 16 diagonal 16 x 16 blocks live in LDS.
+// block into the rows below, applied block by block in increasing s (the
+// same MFMA sequence per block as solving 128-row halves one after the
+// other).  The coupling blocks come from the packed diagonal block in global
+// memory (L2-resident, shared by all workgroups), each loaded by the wave
+// that applies it one or two steps before it is needed.  Only the 16
+// diagonal 16 x 16 blocks live in LDS.
 template <typename TS, int CG, bool UNIT, bool FULL>
 __global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict__ P, int rows,
                                                             TS* __restrict__ B, int64_t off,
