@@ -152,3 +152,21 @@ def test_cpu_interpreter_matches_oracle(variant, m, nb):
     assert oracle.backward_error(0, 0, 0, 0, 1.0, A, B, X) <= 1e-14 * m
     Xo = oracle.trsm_plain(0, 0, 0, 0, 1.0, A, B)
     assert oracle.forward_error(X, Xo) <= 1e-12
+
+
+@pytest.mark.parametrize("nb", [128, 256])
+def test_bench_algorithmic_bytes_follow_the_schedule(nb):
+    """bench.py's algorithmic bytes per product launch (the roofline's
+    denominator) are computed from the same recursive split as the planner's
+    products: same count, same M x K shapes."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench", os.path.join(os.path.dirname(__file__), os.pardir, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n = nrhs = 8192
+    prods = [(rows, cols) for kind, _, rows, _, cols, _ in _tasks("recursive", n, nb) if kind == GEMM]
+    want = sum(8.0 * (m * k + k * nrhs + 2 * m * nrhs) for m, k in prods) / len(prods)
+    assert bench.algorithmic_bytes(n, nrhs, nb) == pytest.approx(want, rel=1e-12)
+    assert len(prods) == n // nb - 1
