@@ -107,8 +107,9 @@ enum {
  * type of A and B (double or float).  Argument numbers for the -i return:
  * dtype 1, side 2, uplo 3, trans 4, diag 5, m 6, n 7, alpha 8, A 9, lda 10,
  * B 11, ldb 12, opts 13, stream 14.  Temporary device memory (at most
- * order(A) * nb elements plus a few KB) is taken from a per-device cache that
- * the library grows on demand and keeps until the process ends.
+ * 1.5 * order(A) * nb elements plus a few KB: the packed diagonal blocks) is
+ * taken from a per-device cache that the library grows on demand and keeps
+ * until the process ends.
  */
 int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                 double alpha, const void* A, int64_t lda, void* B, int64_t ldb,

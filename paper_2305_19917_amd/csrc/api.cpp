@@ -268,7 +268,8 @@ int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, con
     while (i < tasks.size()) {
         const Task& t = tasks[i];
         if (t.kind == TASK_LEAF) {
-            const char* pb = (const char*)packed + (size_t)(t.row0 / kleaf) * kleaf * kleaf * es;
+            const char* pb =
+                (const char*)packed + (size_t)(t.row0 / kleaf) * leaf_block_elems((int)kleaf) * es;
             const double fl = (double)t.rows * t.rows * c.nrhs;
             if (traced(REDSEA_KERNEL_LEAF, fl, s, [&] {
                     return launch_leaf(c.dtype, (int)kleaf, pb, t.rows, c.rhs, t.row0, c.nrhs,
@@ -349,7 +350,7 @@ int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
     const int64_t nblk = (c.k + kleaf - 1) / kleaf;
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
     void* packed = nullptr;
-    int rc = workspace(0, (size_t)nblk * kleaf * kleaf * es, &packed);
+    int rc = workspace(0, (size_t)nblk * leaf_block_elems((int)kleaf) * es, &packed);
     if (rc) return rc;
     if (traced(REDSEA_KERNEL_PACK, 0.0, s, [&] {
             return launch_pack_diag(c.dtype, c.tri, c.k, (int)kleaf, 0, nblk, c.unit, packed, s);

@@ -23,7 +23,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void pack_diag_kernel(const T* __restrict__ A, int64_t off,
                                                         int64_t tr, int64_t tc, int64_t m,
                                                         int nb, int64_t first_blk, int64_t nblk,
-                                                        int unit, T* __restrict__ P) {
+                                                        int unit, int64_t stride,
+                                                        T* __restrict__ P) {
     const int64_t nn = (int64_t)nb * nb;
     for (int64_t blk = blockIdx.y; blk < nblk; blk += gridDim.y) {
         const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -35,7 +36,31 @@ __global__ __launch_bounds__(256) void pack_diag_kernel(const T* __restrict__ A,
         else if (gi >= m) v = (r == c) ? T(1) : T(0);
         else if (r == c && unit) v = T(1);
         else v = A[off + gi * tr + gj * tc];
-        P[blk * nn + idx] = v;
+        P[blk * stride + idx] = v;
+    }
+}
+
+// For 256-row leaves: the 120 strictly lower 16 x 16 blocks (p, s), p > s, of
+// each packed square, negated, in the A-operand order of
+// v_mfma_f64_16x16x4f64: block p(p-1)/2 + s holds, for lane l and k-slice kk,
+// -L(16p + l % 16, 16s + 4kk + l / 16) at [l*4 + kk], so one lane's four
+// k-slices are 32 contiguous bytes.  Reads the square written just before
+// (stream order) and writes behind it.
+template <typename T>
+__global__ __launch_bounds__(256) void pack_frag_kernel(T* __restrict__ P, int64_t nblk,
+                                                        int64_t stride) {
+    constexpr int NP2 = 256;
+    for (int64_t blk = blockIdx.y; blk < nblk; blk += gridDim.y) {
+        const int e = blockIdx.x * 256 + threadIdx.x;  // < 120 * 256 by the grid
+        const int bidx = e >> 8, l = (e >> 2) & 63, kk = e & 3;
+        int p = 1, u = bidx;
+        while (u >= p) {
+            u -= p;
+            ++p;
+        }
+        const int s = u;
+        T* sq = P + blk * stride;
+        sq[NP2 * NP2 + e] = -sq[(16 * s + 4 * kk + (l >> 4)) * NP2 + 16 * p + (l & 15)];
     }
 }
 
@@ -240,9 +265,21 @@ __global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict
         for (int k = 0; k < NBK * 256 / NT; ++k) Ds[tid + k * NT] = t[k];
     }
     __syncthreads();
-    // A operand of k-slice kk for block (p, s): element (16p + c, 16s + 4kk + g)
-    auto lop = [&](int p, int s, int kk) -> double {
-        return -(double)P[(16 * s + 4 * kk + g) * NP2 + 16 * p + c];
+    // A operands of block (p, s), k-slices 0..3, from the fragment-ordered
+    // copy behind the square (one 32- or 16-byte load per lane)
+    const TS* F = P + NP2 * NP2;
+    auto lop4 = [&](int p, int s, double* out) {
+        const TS* q = F + (p * (p - 1) / 2 + s) * 256 + lane * 4;
+        if constexpr (sizeof(TS) == 8) {
+            const v4d v = *(const v4d*)q;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) out[kk] = v[kk];
+        } else {
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const v4f v = *(const v4f*)q;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) out[kk] = (double)v[kk];
+        }
     };
     // Coupling blocks the owner of block s applies right after solving it:
     // (p, s - 1) and (p, s) for its blocks p = 2j + (s & 1) > s.  Loaded two
@@ -251,18 +288,13 @@ __global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict
     double adq[2][NJ][2][4];
     auto load_deferred = [&](int s) {
 #pragma unroll
-        for (int j = (s >> 1) + 1; j < NJ; ++j)
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                if (s > 0) adq[(s >> 1) & 1][j][0][kk] = lop(2 * j + (s & 1), s - 1, kk);
-                adq[(s >> 1) & 1][j][1][kk] = lop(2 * j + (s & 1), s, kk);
-            }
+        for (int j = (s >> 1) + 1; j < NJ; ++j) {
+            if (s > 0) lop4(2 * j + (s & 1), s - 1, adq[(s >> 1) & 1][j][0]);
+            lop4(2 * j + (s & 1), s, adq[(s >> 1) & 1][j][1]);
+        }
     };
     double ac[4];  // block (s + 1, s), applied by the owner of block s + 1
-    auto load_critical = [&](int s) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) ac[kk] = lop(s + 1, s, kk);
-    };
+    auto load_critical = [&](int s) { lop4(s + 1, s, ac); };
     if (v == 0) {
         load_deferred(0);
     } else {
@@ -378,14 +410,26 @@ __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__
 hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int64_t first_blk,
                             int64_t nblk, bool unit, void* packed, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
-    const int64_t nn = (int64_t)nb * nb;
-    dim3 grid((unsigned)((nn + 255) / 256), (unsigned)(nblk < 65535 ? nblk : 65535)), block(256);
+    const int64_t nn = (int64_t)nb * nb, stride = leaf_block_elems(nb);
+    const unsigned gy = (unsigned)(nblk < 65535 ? nblk : 65535);
+    dim3 grid((unsigned)((nn + 255) / 256), gy), block(256);
     if (dtype == 0)
         hipLaunchKernelGGL(pack_diag_kernel<double>, grid, block, 0, s, (const double*)T.base,
-                           T.off, T.tr, T.tc, m, nb, first_blk, nblk, unit ? 1 : 0, (double*)packed);
+                           T.off, T.tr, T.tc, m, nb, first_blk, nblk, unit ? 1 : 0, stride,
+                           (double*)packed);
     else
         hipLaunchKernelGGL(pack_diag_kernel<float>, grid, block, 0, s, (const float*)T.base,
-                           T.off, T.tr, T.tc, m, nb, first_blk, nblk, unit ? 1 : 0, (float*)packed);
+                           T.off, T.tr, T.tc, m, nb, first_blk, nblk, unit ? 1 : 0, stride,
+                           (float*)packed);
+    if (nb == 256) {
+        dim3 fgrid(120, gy);
+        if (dtype == 0)
+            hipLaunchKernelGGL(pack_frag_kernel<double>, fgrid, block, 0, s, (double*)packed, nblk,
+                               stride);
+        else
+            hipLaunchKernelGGL(pack_frag_kernel<float>, fgrid, block, 0, s, (float*)packed, nblk,
+                               stride);
+    }
     return hipGetLastError();
 }
 

@@ -20,16 +20,24 @@ struct RhsView {
     int64_t off, br, bc;
 };
 
+// Elements of one packed leaf block: the nb x nb square, for nb = 256
+// followed by its 120 off-diagonal 16 x 16 blocks in MFMA A-operand order.
+inline int64_t leaf_block_elems(int nb) {
+    return (int64_t)nb * nb + (nb == 256 ? 120 * 256 : 0);
+}
+
 // Copies the diagonal blocks of T into `packed`: block p (rows
-// [p*nb, p*nb+nb)) becomes an nb x nb column-major square whose lower
-// triangle holds T and whose rows past m are the identity.  nblk blocks.
-// unit: the diagonal is taken as one and not read.
+// [p*nb, p*nb+nb)) becomes, at p * leaf_block_elems(nb), an nb x nb
+// column-major square whose lower triangle holds T and whose rows past m are
+// the identity (for nb = 256 followed by the negated off-diagonal 16 x 16
+// blocks in MFMA A-operand order).  nblk blocks.  unit: the diagonal is taken
+// as one and not read.
 hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int64_t first_blk,
                             int64_t nblk, bool unit, void* packed, hipStream_t s);
 
 // Solves the leaf at rows [row0, row0+rows) for all ncols columns, reading the
-// packed diagonal block `pblk` (nb x nb, nb one of 16, 32, 64, 128, 256;
-// rows <= nb).  unit: skip the division.
+// packed leaf block `pblk` (leaf_block_elems(nb) elements, nb one of 16, 32,
+// 64, 128, 256; rows <= nb).  unit: skip the division.
 hipError_t launch_leaf(int dtype, int nb, const void* pblk, int64_t rows, const RhsView& B,
                        int64_t row0, int64_t ncols, bool unit, hipStream_t s);
 
