@@ -88,7 +88,8 @@ def test_two_wave_leaf_ragged(nb, dtype):
     block) and span several leaves; the column counts leave partial column
     groups."""
     bar = 1e-14 if dtype == np.float64 else 5e-6
-    for k, nrhs in [(100, 45), (300, 17), (429, 33), (512, 64), (700, 1), (1100, 70)]:
+    for k, nrhs in [(100, 45), (256, 16), (257, 3), (300, 17), (429, 33), (512, 64), (700, 1),
+                    (1100, 70)]:
         _say("two-wave leaf", nb, dtype.__name__, k, nrhs)
         L = synth.dominant_lower(k, (15, k, 0)).astype(dtype)
         B = synth.rhs_normal(k, nrhs, (15, k, 1)).astype(dtype)
