@@ -58,7 +58,10 @@ typedef enum { REDSEA_LOWER = 0, REDSEA_UPPER = 1 } redsea_uplo;
 /* For real data the conjugate transpose equals the transpose. */
 typedef enum { REDSEA_NOTRANS = 0, REDSEA_TRANS = 1, REDSEA_CONJTRANS = 2 } redsea_trans;
 typedef enum { REDSEA_NONUNIT = 0, REDSEA_UNIT = 1 } redsea_diag;
-typedef enum { REDSEA_F64 = 0, REDSEA_F32 = 1 } redsea_dtype;
+/* REDSEA_BF16 is accepted by redsea_gemm_update only: a BF16 matrix operand
+ * with FP32 right-hand sides and result (the product of the BF16 refinement
+ * mode). */
+typedef enum { REDSEA_F64 = 0, REDSEA_F32 = 1, REDSEA_BF16 = 2 } redsea_dtype;
 
 /* Model of computation (paper Sec. V). */
 typedef enum {
@@ -77,12 +80,15 @@ typedef enum {
 
 /* Solver options; a NULL pointer means every field AUTO.  nb is the leaf
  * (diagonal block) order; 0 = AUTO, otherwise one of 16, 32, 64, 128, 256,
- * 512.  kappa is the caller's estimate of the condition number of op(A)
- * (0 = unknown: the library then uses max|a_ii| / min|a_ii|); it only
- * informs the automatic choice, never the arithmetic.  When variant, nb and
- * precision are all AUTO the learned picker chooses them (see
- * redsea_pick); an AUTO nb beside a fixed variant or precision is 256 for
- * order(A) > 128, else 128. */
+ * 512.  kappa is the caller's estimate of the condition number of op(A); it
+ * only informs the automatic choice, never the arithmetic.  When variant, nb
+ * and precision are all AUTO the learned picker chooses them (see
+ * redsea_pick); if kappa is then 0 (unknown) the library computes
+ * max|a_ii| / min|a_ii| (a lower bound on the condition number of a
+ * triangular matrix; 1 for a unit diagonal) on the device and waits for that
+ * value, so an AUTO call with kappa = 0 synchronizes the stream once.  An
+ * AUTO nb beside a fixed variant or precision is 256 for order(A) > 128,
+ * else 128. */
 typedef struct {
     int variant;   /* redsea_variant   */
     int nb;        /* leaf size or 0   */
@@ -108,8 +114,13 @@ enum {
  * dtype 1, side 2, uplo 3, trans 4, diag 5, m 6, n 7, alpha 8, A 9, lda 10,
  * B 11, ldb 12, opts 13, stream 14.  Temporary device memory (at most
  * 1.5 * order(A) * nb elements plus a few KB: the packed diagonal blocks) is
- * taken from a per-device cache that the library grows on demand and keeps
- * until the process ends.
+ * taken from a buffer the library keeps per (device, stream) until the
+ * process ends.  It grows in stream order (hipFreeAsync of the old buffer,
+ * hipMallocAsync of the new one, both on `stream`), so calls on different
+ * streams may run concurrently and calls on one stream never wait for the
+ * device.  A call on a stream that is being captured into a HIP graph returns
+ * REDSEA_ERR_UNSUPPORTED (a cached buffer could be freed before the graph is
+ * replayed); a batched plan (below) owns its memory and may be captured.
  */
 int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                 double alpha, const void* A, int64_t lda, void* B, int64_t ldb,
@@ -140,8 +151,11 @@ int redsea_trsm_batched(int dtype, int side, int uplo, int trans, int diag, int6
  * Batched plan: the host work of redsea_trsm_batched (argument checks,
  * canonical descriptors, task order, one synchronous upload) done once, so
  * that redsea_batched_plan_run() is kernel launches only and may be captured
- * in a hipGraph and replayed.  The plan keeps the device pointers it was
- * created with; the caller keeps those buffers alive and unchanged in shape.
+ * in a hipGraph and replayed: every device buffer a run uses (descriptors,
+ * task list, the packed diagonal blocks of systems above order 1024) is
+ * allocated by create and owned by the plan.  The plan keeps the device
+ * pointers it was created with; the caller keeps those buffers alive and
+ * unchanged in shape.
  * create: arguments 1-13 as in redsea_trsm_batched, opts 14, out 15 (HOST
  * pointer receiving the plan).  run: plan 1, info 2 (DEVICE int[count]),
  * stream 3; calls of one plan must not overlap in time.  destroy waits for
@@ -173,7 +187,7 @@ typedef struct {
  * convergence it falls back to the FP64 solve.  inner = 0 picks
  * automatically.  work/work_bytes: optional DEVICE workspace of at least
  * redsea_trsm_mixed_workspace_bytes(...) bytes; NULL uses the library's
- * cache.  stats: optional HOST struct.  This call synchronizes the stream
+ * per-(device, stream) buffer as redsea_trsm does.  stats: optional HOST struct.  This call synchronizes the stream
  * once per refinement step to read the convergence test.  Argument numbers:
  * side 1, uplo 2, trans 3, diag 4, m 5, n 6, alpha 7, A 8, lda 9, B 10,
  * ldb 11, inner 12, tol 13, max_iter 14, work 15, work_bytes 16, stats 17,
@@ -211,8 +225,12 @@ int64_t redsea_schedule(int variant, int64_t m, int nb, int64_t* tasks, int64_t 
  * sides) performs, on the same MFMA kernels the solver uses.  op(A) is M x K:
  * A[i + k*lda] (transa = 0) or A[k + i*lda] (transa = 1).  transx = 0: X is
  * K x N at X[k + j*ldx] and C is M x N at C[i + j*ldc]; transx = 1: both are
- * stored transposed, X[j + k*ldx] and C[j + i*ldc].  tile selects a kernel
- * tile configuration (0 .. 17) or -1 for the default.  Argument numbers:
+ * stored transposed, X[j + k*ldx] and C[j + i*ldc].  dtype REDSEA_F64 and
+ * REDSEA_F32: A, X and C of that type.  dtype REDSEA_BF16: A holds BF16
+ * values, X and C FP32; each X value is rounded to BF16 (nearest even) and
+ * the products of BF16 values are accumulated in FP32 before C is updated
+ * (the product of the BF16 refinement mode).  tile selects a kernel tile
+ * configuration (0 .. 17) or -1 for the default (BF16: -1 only).  Argument numbers:
  * dtype 1, transa 2, transx 3, M 4, N 5, K 6, A 7, lda 8, X 9, ldx 10, C 11,
  * ldc 12, tile 13, stream 14.  Asynchronous on stream.
  */
@@ -307,7 +325,6 @@ int redsea_mlp_adam(float* params, const float* grad, float* m, float* v, int64_
 int redsea_pick(int dtype, int64_t n, int64_t nrhs, double kappa, int* confident);
 int redsea_mlp_load(const char* path);
 
-/* Library version as "major.minor.patch". */
 /* Diagnostic, not part of the solver: the achievable matrix-core rate.
  * Launches, asynchronously on `stream`, 4096 workgroups of four waves, each
  * wave running eight independent chains of `iters` (rounded up to a multiple
@@ -319,8 +336,9 @@ int redsea_mlp_load(const char* path);
  * a bad dtype or iters <= 0, -3 for a missing or short `out`, -100 when the
  * launch fails.  The MI355X datasheet roofs are 78.6 (FP64) and 157.3 (FP32)
  * TFLOP/s. */
-int64_t redsea_mfma_peak(int dtype, int64_t iters, void* out, int64_t out_elems, hipStream_t stream);
+int64_t redsea_mfma_peak(int dtype, int64_t iters, void* out, int64_t out_elems, void* stream);
 
+/* Library version as "major.minor.patch". */
 const char* redsea_version(void);
 
 #ifdef __cplusplus

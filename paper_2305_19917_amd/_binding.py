@@ -276,6 +276,9 @@ def trsm_mixed(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0
 def gemm_update(A, X, C, transa=False, transx=False, tile: int = -1, stream=None):
     """In place C := C - op(A) op(X) on the library's MFMA kernels.
 
+    A bfloat16 A selects the BF16 product (X and C float32, X rounded to
+    BF16, FP32 accumulation).
+
     With transx, X and C are passed as their transposes (row-major storage):
     shapes are then X^T (N x K) and C^T (N x M)."""
     if transx:
@@ -283,7 +286,9 @@ def gemm_update(A, X, C, transa=False, transx=False, tile: int = -1, stream=None
     else:
         M, N = C.shape
     K = A.shape[0] if transa else A.shape[1]
-    rc = lib().redsea_gemm_update(_dtype_code(C), int(bool(transa)), int(bool(transx)), M, N, K,
+    import torch
+    code = 2 if A.dtype == torch.bfloat16 else _dtype_code(C)
+    rc = lib().redsea_gemm_update(code, int(bool(transa)), int(bool(transx)), M, N, K,
                                   A.data_ptr(), _ld(A), X.data_ptr(), _ld(X), C.data_ptr(), _ld(C),
                                   int(tile), _stream(stream))
     _check(rc)

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -22,39 +23,59 @@
 namespace redsea {
 
 // ------------------------------------------------------------------ workspace
+// One buffer per (device, stream, slot).  Solves on different streams never
+// share memory, and a buffer grows in stream order: the old one is released
+// with hipFreeAsync and the new one taken with hipMallocAsync on the same
+// stream, so work already queued there finishes with the old buffer first.
+// A lease holds the entry's lock while its holder enqueues the work that
+// uses the buffer, so a second host thread on the same stream cannot release
+// it in between.  On a stream that is being captured into a graph a cached
+// pointer would outlive its buffer (a later growth frees it), so the lease is
+// refused there: graph capture goes through the entry point with static
+// scratch memory, or the batched plan, which owns its memory.
 namespace {
 
-struct DevBuf {
+struct WsEntry {
+    std::mutex mu;
     void* ptr = nullptr;
     size_t bytes = 0;
 };
 
 std::mutex g_ws_mu;
-std::map<std::pair<int, int>, DevBuf> g_ws;  // (device, slot) -> buffer
+std::map<std::tuple<int, uintptr_t, int>, std::unique_ptr<WsEntry>> g_ws;
 
 }  // namespace
 
-int workspace(int slot, size_t bytes, void** out) {
+int workspace(int slot, size_t bytes, hipStream_t s, WsLease& out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return REDSEA_ERR_HIP;
-    std::lock_guard<std::mutex> lock(g_ws_mu);
-    DevBuf& b = g_ws[{dev, slot}];
-    if (b.bytes < bytes) {
-        if (b.ptr) {
-            if (hipDeviceSynchronize() != hipSuccess) return REDSEA_ERR_HIP;
-            if (hipFree(b.ptr) != hipSuccess) return REDSEA_ERR_HIP;
-            b.ptr = nullptr;
-            b.bytes = 0;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return REDSEA_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone) return REDSEA_ERR_UNSUPPORTED;
+    WsEntry* e = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mu);
+        auto& slotp = g_ws[std::make_tuple(dev, (uintptr_t)s, slot)];
+        if (!slotp) slotp.reset(new WsEntry);
+        e = slotp.get();
+    }
+    std::unique_lock<std::mutex> lock(e->mu);
+    if (e->bytes < bytes) {
+        if (e->ptr) {
+            if (hipFreeAsync(e->ptr, s) != hipSuccess) return REDSEA_ERR_HIP;
+            e->ptr = nullptr;
+            e->bytes = 0;
         }
-        size_t want = bytes + bytes / 4;
-        if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        const size_t want = bytes + bytes / 4;
+        if (hipMallocAsync(&e->ptr, want, s) != hipSuccess) {
             (void)hipGetLastError();
-            b.ptr = nullptr;
+            e->ptr = nullptr;
             return REDSEA_ERR_ALLOC;
         }
-        b.bytes = want;
+        e->bytes = want;
     }
-    *out = b.ptr;
+    out.lock = std::move(lock);
+    out.ptr = e->ptr;
     return REDSEA_OK;
 }
 
@@ -344,19 +365,30 @@ int column_groups(const Canon& c) {
 // substitution of the other contend, and measured slower.
 static int64_t leaf_rows(int64_t nb) { return nb >= 256 ? 256 : std::min<int64_t>(nb, 128); }
 
-int execute(const Canon& c, int variant, int64_t nb, hipStream_t s) {
+size_t packed_bytes(const Canon& c, int64_t nb) {
+    const int64_t kleaf = leaf_rows(nb);
+    const int64_t nblk = (c.k + kleaf - 1) / kleaf;
+    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
+    return (size_t)nblk * leaf_block_elems((int)kleaf) * es;
+}
+
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed) {
     const int64_t kleaf = leaf_rows(nb);
     const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
     const int64_t nblk = (c.k + kleaf - 1) / kleaf;
-    const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
-    void* packed = nullptr;
-    int rc = workspace(0, (size_t)nblk * leaf_block_elems((int)kleaf) * es, &packed);
-    if (rc) return rc;
+    int rc = REDSEA_OK;
+    WsLease lease;
+    if (!packed) {
+        if ((rc = workspace(0, packed_bytes(c, nb), s, lease))) return rc;
+        packed = lease.ptr;
+    }
     if (traced(REDSEA_KERNEL_PACK, 0.0, s, [&] {
             return launch_pack_diag(c.dtype, c.tri, c.k, (int)kleaf, 0, nblk, c.unit, packed, s);
         }) != hipSuccess)
         return REDSEA_ERR_HIP;
-    const int groups = column_groups(c);
+    // helper streams only when the library owns the memory: callers that
+    // bring it (a batched plan, static scratch) may be capturing a graph
+    const int groups = lease.ptr ? column_groups(c) : 1;
     if (groups == 1) return run_tasks(c, tasks, kleaf, packed, s);
 
     hipStream_t side[4];
@@ -418,6 +450,28 @@ int tuned_candidate(int dtype, int64_t k, int64_t nrhs, double kappa, hipStream_
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tuned[key] = pick;
     return pick;
+}
+
+// Condition estimate from the diagonal alone: for a triangular matrix the
+// diagonal entries are the eigenvalues, so max|t_ii| / min|t_ii| is a lower
+// bound on its condition number in any norm.  O(k) reads on the device and one
+// wait for the two extremes; a unit diagonal gives 1, a zero or non-finite
+// extreme an infinite estimate.
+int diag_kappa(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               const void* A, int64_t lda, hipStream_t s, double* kappa) {
+    *kappa = 1.0;
+    if (diag == REDSEA_UNIT) return REDSEA_OK;
+    const Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, nullptr, 1);
+    WsLease lease;
+    int rc = workspace(2, 2 * sizeof(double), s, lease);
+    if (rc) return rc;
+    double h[2] = {0.0, 0.0};
+    if (launch_diag_extremes(dtype, c.tri, c.k, (double*)lease.ptr, s) != hipSuccess ||
+        hipMemcpyAsync(h, lease.ptr, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return REDSEA_ERR_HIP;
+    *kappa = (h[1] > 0.0 && std::isfinite(h[0])) ? h[0] / h[1] : INFINITY;
+    return REDSEA_OK;
 }
 
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
@@ -506,7 +560,9 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
         // not confident); a condition estimate, when not given, is taken as
         // that of a diagonally dominant matrix of this order
         const int64_t k = side == REDSEA_LEFT ? m : n, nrhs = side == REDSEA_LEFT ? n : m;
-        const double kap = chosen.kappa > 0.0 ? chosen.kappa : 4.5 * (double)k;
+        double kap = chosen.kappa;
+        if (!(kap > 0.0) && (rc = diag_kappa(dtype, side, uplo, trans, diag, m, n, A, lda, s, &kap)))
+            return rc;
         int confident = 0;
         int cand = pick_candidate(dtype, k, nrhs, kap, &confident);
         if (!confident) {
@@ -574,7 +630,7 @@ int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds) {
 int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, int64_t K,
                        const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
                        int64_t ldc, int tile, void* stream) {
-    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32 && dtype != REDSEA_BF16) return -1;
     if (transa != 0 && transa != 1) return -2;
     if (transx != 0 && transx != 1) return -3;
     if (M < 0) return -4;
@@ -583,7 +639,7 @@ int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, 
     if (lda < std::max<int64_t>(1, transa ? K : M)) return -8;
     if (ldx < std::max<int64_t>(1, transx ? N : K)) return -10;
     if (ldc < std::max<int64_t>(1, transx ? N : M)) return -12;
-    if (tile < -1 || tile >= gemm_tile_count()) return -13;
+    if (tile < -1 || tile >= gemm_tile_count() || (dtype == REDSEA_BF16 && tile != -1)) return -13;
     if (M == 0 || N == 0 || K == 0) return REDSEA_OK;
     if (!A) return -7;
     if (!X) return -9;
@@ -591,6 +647,12 @@ int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, 
     GemmArgs g{M, N, K, A, lda, X, ldx, C, ldc};
     const double fl = 2.0 * M * N * K;
     hipStream_t s = (hipStream_t)stream;
+    if (dtype == REDSEA_BF16)
+        return traced(REDSEA_KERNEL_GEMM, fl, s, [&] {
+                   return launch_gemm_bf16(transa != 0, transx != 0, g, s);
+               }) == hipSuccess
+                   ? REDSEA_OK
+                   : REDSEA_ERR_HIP;
     return traced(REDSEA_KERNEL_GEMM, fl, s, [&] {
                return launch_gemm(dtype, transa != 0, transx != 0, g, s, tile);
            }) == hipSuccess

@@ -30,6 +30,10 @@ struct redsea_batch_plan {
     std::vector<redsea::Canon> big;
     std::vector<int64_t> big_index;
     int variant = 1, nb = 128;
+    // packed diagonal blocks of the large systems (solved one after another
+    // on the run's stream, so one buffer of the largest size serves all);
+    // owned by the plan so that a run allocates nothing
+    void* packed = nullptr;
 };
 
 namespace redsea {
@@ -128,6 +132,14 @@ int redsea_batched_plan_create(int dtype, int side, int uplo, int trans, int dia
         sys.resize(std::max<size_t>(sys.size(), (size_t)i + 1));
         sys[i] = d;
     }
+    size_t big_bytes = 0;
+    for (const Canon& c : P->big) big_bytes = std::max(big_bytes, packed_bytes(c, pick_nb(P->nb, c.k)));
+    if (big_bytes > 0 && hipMalloc(&P->packed, big_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        P->packed = nullptr;
+        redsea_batched_plan_destroy(P);
+        return REDSEA_ERR_ALLOC;
+    }
     std::stable_sort(work.begin(), work.end(),
                      [](const std::pair<double, BatchTask>& x, const std::pair<double, BatchTask>& y) {
                          return x.first > y.first;
@@ -180,7 +192,7 @@ int redsea_batched_plan_run(redsea_batch_plan* P, int* info, void* stream) {
             launch_scale(P->dtype, c.B, rows, cols, c.ldb, P->alpha, s) != hipSuccess)
             return REDSEA_ERR_HIP;
         if (P->alpha != 0.0) {
-            int rc = execute(c, P->variant, pick_nb(P->nb, c.k), s);
+            int rc = execute(c, P->variant, pick_nb(P->nb, c.k), s, P->packed);
             if (rc) return rc;
         }
         if (launch_check_finite(P->dtype, c.B, rows, cols, c.ldb, info + P->big_index[i],
@@ -199,6 +211,7 @@ void redsea_batched_plan_destroy(redsea_batch_plan* P) {
     if (P->d_sys) (void)hipFree(P->d_sys);
     if (P->d_tasks) (void)hipFree(P->d_tasks);
     if (P->d_counter) (void)hipFree(P->d_counter);
+    if (P->packed) (void)hipFree(P->packed);
     (void)hipSetDevice(cur);
     delete P;
 }

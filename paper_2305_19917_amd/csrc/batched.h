@@ -25,10 +25,8 @@ struct BatchTask {
 constexpr int64_t kBatchMaxOrder = 1024;  // panel of 16 columns in LDS
 
 hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_t s);
-size_t batched_lds_bytes(int64_t kmax);
 hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
                           int ntasks, int* counter, int* info, int64_t kmax, double alpha,
                           int grid, hipStream_t s);
-hipError_t batched_set_lds_limit(int dtype, bool unit, size_t bytes);
 
 }  // namespace redsea

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "../../include/redsea.h"
@@ -37,8 +38,18 @@ Canon canonicalize(int dtype, int side, int uplo, int trans, int diag, int64_t m
                    const void* A, int64_t lda, void* B, int64_t ldb);
 GemmArgs gemm_args(const Canon& c, int64_t r0, int64_t R, int64_t c0, int64_t K);
 const std::vector<Task>& plan_for(int variant, int64_t k, int64_t nb, int64_t kleaf);
-int execute(const Canon& c, int variant, int64_t nb, hipStream_t s);
-int workspace(int slot, size_t bytes, void** out);
+// Library workspace for one stream (see api.cpp): `ptr` stays valid, and no
+// other host thread may regrow it, while the lease is held.
+struct WsLease {
+    std::unique_lock<std::mutex> lock;
+    void* ptr = nullptr;
+};
+int workspace(int slot, size_t bytes, hipStream_t s, WsLease& out);
+// Bytes of packed diagonal blocks execute() needs for this solve.
+size_t packed_bytes(const Canon& c, int64_t nb);
+// Runs the solve on stream s.  packed: device memory of packed_bytes(c, nb)
+// bytes for the diagonal blocks, or null to take it from the workspace.
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed = nullptr);
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
 int pick_nb(int requested, int64_t k);

@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
         for (int p = 0; p < nblk; ++p) {
             v4d acc;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = alpha * bget(16 * p + g + 4 * r);
+            for (int r = 0; r < 4; ++r)
+                acc[r] = alpha != 0.0 ? alpha * bget(16 * p + g + 4 * r) : 0.0;  // BLAS: B := 0
             if (alpha != 0.0) {
                 // diagonal block (identity past the order) and the reciprocals
                 // of its diagonal; independent of the products below
@@ -218,38 +219,26 @@ hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_
     return hipGetLastError();
 }
 
-size_t batched_lds_bytes(int64_t kmax) {
-    (void)kmax;
-    return 0;  // every buffer is static: 4 waves x (gather + diagonal block)
-}
-
 hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
                           int ntasks, int* counter, int* info, int64_t kmax, double alpha,
                           int grid, hipStream_t s) {
-    const size_t lds = batched_lds_bytes(kmax);
+    (void)kmax;
     if (dtype == 0) {
         if (unit)
-            hipLaunchKernelGGL((batched_kernel<double, true>), dim3(grid), dim3(256), lds, s, sys,
+            hipLaunchKernelGGL((batched_kernel<double, true>), dim3(grid), dim3(256), 0, s, sys,
                                tasks, ntasks, counter, info, alpha);
         else
-            hipLaunchKernelGGL((batched_kernel<double, false>), dim3(grid), dim3(256), lds, s, sys,
+            hipLaunchKernelGGL((batched_kernel<double, false>), dim3(grid), dim3(256), 0, s, sys,
                                tasks, ntasks, counter, info, alpha);
     } else {
         if (unit)
-            hipLaunchKernelGGL((batched_kernel<float, true>), dim3(grid), dim3(256), lds, s, sys,
+            hipLaunchKernelGGL((batched_kernel<float, true>), dim3(grid), dim3(256), 0, s, sys,
                                tasks, ntasks, counter, info, alpha);
         else
-            hipLaunchKernelGGL((batched_kernel<float, false>), dim3(grid), dim3(256), lds, s, sys,
+            hipLaunchKernelGGL((batched_kernel<float, false>), dim3(grid), dim3(256), 0, s, sys,
                                tasks, ntasks, counter, info, alpha);
     }
     return hipGetLastError();
-}
-
-hipError_t batched_set_lds_limit(int dtype, bool unit, size_t bytes) {
-    (void)dtype;
-    (void)unit;
-    (void)bytes;
-    return hipSuccess;
 }
 
 }  // namespace redsea

@@ -405,7 +405,51 @@ __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__
     if (threadIdx.x == 0) info[0] = bad ? code : 0;
 }
 
+// out[0] = max |T(i, i)|, out[1] = min |T(i, i)| over the k diagonal entries
+// (a NaN entry makes both NaN).  One workgroup; max and min do not depend on
+// the reduction order.
+template <typename T>
+__global__ __launch_bounds__(256) void diag_extremes_kernel(const T* __restrict__ a, int64_t off,
+                                                            int64_t step, int64_t k,
+                                                            double* __restrict__ out) {
+    __shared__ double mx[256], mn[256];
+    double hi = 0.0, lo = __builtin_inf();
+    for (int64_t i = threadIdx.x; i < k; i += 256) {
+        const double v = __builtin_fabs((double)a[off + i * step]);
+        hi = (v > hi || v != v) ? v : hi;
+        lo = (v < lo || v != v) ? v : lo;
+    }
+    mx[threadIdx.x] = hi;
+    mn[threadIdx.x] = lo;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double h = mx[threadIdx.x + w], l = mn[threadIdx.x + w];
+            if (h > mx[threadIdx.x] || h != h) mx[threadIdx.x] = h;
+            if (l < mn[threadIdx.x] || l != l) mn[threadIdx.x] = l;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = mx[0];
+        out[1] = mn[0];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* out,
+                                hipStream_t s) {
+    if (k <= 0) return hipSuccess;
+    const int64_t step = T.tr + T.tc;  // (i, i) -> (i + 1, i + 1)
+    if (dtype == 0)
+        hipLaunchKernelGGL(diag_extremes_kernel<double>, dim3(1), dim3(256), 0, s,
+                           (const double*)T.base, T.off, step, k, out);
+    else
+        hipLaunchKernelGGL(diag_extremes_kernel<float>, dim3(1), dim3(256), 0, s,
+                           (const float*)T.base, T.off, step, k, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack_diag(int dtype, const TriView& T, int64_t m, int nb, int64_t first_blk,
                             int64_t nblk, bool unit, void* packed, hipStream_t s) {

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void mfma_peak_kernel(int64_t iters, T* out) {
 }  // namespace redsea
 
 extern "C" int64_t redsea_mfma_peak(int dtype, int64_t iters, void* out, int64_t out_elems,
-                                    hipStream_t stream) {
+                                    void* stream_ptr) {
+    hipStream_t stream = (hipStream_t)stream_ptr;
     using namespace redsea;
     const int64_t grid = 4096;  // 16 workgroups of four waves per CU
     if ((dtype != REDSEA_F64 && dtype != REDSEA_F32) || iters <= 0) return -1;

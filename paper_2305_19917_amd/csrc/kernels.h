@@ -84,6 +84,10 @@ hipError_t launch_gemm_group(int dtype, bool a_trans, bool rhs_trans, const Gemm
 hipError_t launch_scale(int dtype, void* b, int64_t m, int64_t n, int64_t ldb, double alpha,
                         hipStream_t s);
 
+// out[0] := max |T(i, i)|, out[1] := min |T(i, i)| over i < k (device doubles).
+hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* out,
+                                hipStream_t s);
+
 // info[0] := 0 if every entry of the m x n matrix is finite, else `code`.
 hipError_t launch_check_finite(int dtype, const void* b, int64_t m, int64_t n, int64_t ldb,
                                int* info, int code, hipStream_t s);

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -58,26 +59,42 @@ MixedLayout layout(int64_t m, int64_t n, int64_t k, int64_t nrhs, bool bf16) {
     return L;
 }
 
-// Pinned host staging for the per-iteration norm read-back (per device).
+// Pinned host staging for the per-iteration norm read-back, one buffer per
+// (device, stream) like the device workspace.  The caller holds the lease
+// (the entry's lock) for the whole solve; every copy into the buffer is
+// waited for before the solve returns, so growth can free the old one.
+struct PinEntry {
+    std::mutex mu;
+    double* ptr = nullptr;
+    size_t doubles = 0;
+};
 std::mutex g_pin_mu;
-std::map<int, std::pair<double*, size_t>> g_pin;
+std::map<std::pair<int, uintptr_t>, std::unique_ptr<PinEntry>> g_pin;
 
-int pinned(size_t doubles, double** out) {
+int pinned(size_t doubles, hipStream_t s, std::unique_lock<std::mutex>& held, double** out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return REDSEA_ERR_HIP;
-    std::lock_guard<std::mutex> lock(g_pin_mu);
-    auto& p = g_pin[dev];
-    if (p.second < doubles) {
-        if (p.first) (void)hipHostFree(p.first);
-        p.first = nullptr;
-        p.second = 0;
-        if (hipHostMalloc((void**)&p.first, doubles * 8, hipHostMallocDefault) != hipSuccess) {
+    PinEntry* e = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_pin_mu);
+        auto& p = g_pin[{dev, (uintptr_t)s}];
+        if (!p) p.reset(new PinEntry);
+        e = p.get();
+    }
+    std::unique_lock<std::mutex> lock(e->mu);
+    if (e->doubles < doubles) {
+        if (e->ptr) (void)hipHostFree(e->ptr);
+        e->ptr = nullptr;
+        e->doubles = 0;
+        if (hipHostMalloc((void**)&e->ptr, doubles * 8, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
+            e->ptr = nullptr;
             return REDSEA_ERR_ALLOC;
         }
-        p.second = doubles;
+        e->doubles = doubles;
     }
-    *out = p.first;
+    held = std::move(lock);
+    *out = e->ptr;
     return REDSEA_OK;
 }
 
@@ -99,11 +116,13 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     const bool unit = diag == REDSEA_UNIT;
     const MixedLayout L = layout(m, n, k, nrhs, bf16);
     char* ws = (char*)work;
+    WsLease lease;
     if (ws) {
         if (work_bytes < L.total) return -16;
     } else {
-        int rc = workspace(1, L.total, (void**)&ws);
+        int rc = workspace(1, L.total, s, lease);
         if (rc) return rc;
+        ws = (char*)lease.ptr;
     }
     float* a32 = (float*)(ws + L.a32);
     void* a16 = ws + L.a16;
@@ -116,7 +135,8 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     double* scal = (double*)(ws + L.scal);
     double* rowsum = (double*)(ws + L.rowsum);
     double* host = nullptr;
-    int rc = pinned((size_t)3 * nrhs + (size_t)k, &host);
+    std::unique_lock<std::mutex> pin_lock;
+    int rc = pinned((size_t)3 * nrhs + (size_t)k, s, pin_lock, &host);
     if (rc) return rc;
     double* h_r = host;
     double* h_x = host + nrhs;

@@ -180,9 +180,10 @@ int redsea_mlp_forward(const float* params, const float* X, int64_t nb, float* Y
     if (!X) return -2;
     if (!Y) return -4;
     hipStream_t s = (hipStream_t)stream;
-    float* tmp = nullptr;
-    int rc = workspace(3, (size_t)nb * (64 + 64) * sizeof(float), (void**)&tmp);
+    WsLease lease;
+    int rc = workspace(3, (size_t)nb * (64 + 64) * sizeof(float), s, lease);
     if (rc) return rc;
+    float* tmp = (float*)lease.ptr;
     return mlp_forward_dev(params, X, nb, tmp, tmp + nb * 64, Y, s) == hipSuccess ? REDSEA_OK
                                                                                  : REDSEA_ERR_HIP;
 }
@@ -196,11 +197,13 @@ int redsea_mlp_grad(const float* params, const float* X, const float* T, const f
     if (!mask) return -4;
     if (!grad) return -6;
     if (!loss) return -7;
-    float* tmp = nullptr;
-    int rc = workspace(4, ((size_t)nb * (64 + 64 + 45 + 45 + 64 + 64) + 1) * sizeof(float),
-                       (void**)&tmp);
+    hipStream_t s = (hipStream_t)stream;
+    WsLease lease;
+    int rc = workspace(4, ((size_t)nb * (64 + 64 + 45 + 45 + 64 + 64) + 1) * sizeof(float), s,
+                       lease);
     if (rc) return rc;
-    return mlp_grad_dev(params, X, T, mask, nb, grad, loss, tmp, (hipStream_t)stream) ==
+    float* tmp = (float*)lease.ptr;
+    return mlp_grad_dev(params, X, T, mask, nb, grad, loss, tmp, s) ==
                    hipSuccess
                ? REDSEA_OK
                : REDSEA_ERR_HIP;

@@ -111,3 +111,43 @@ def test_picker_outside_trained_shapes_takes_default_schedule():
         assert (var.value, nb.value, prec.value) == (1, want_nb, 1), (n, nrhs, c)
     c = L.redsea_pick(0, 2000, 300, 9000.0, ctypes.byref(conf))
     assert 0 <= c < 45
+
+
+def _consumer_source():
+    names = _declared()
+    fns = ",\n    ".join("(fp)%s" % n for n in names)
+    return """#include "redsea.h"
+#include <stdio.h>
+#include <string.h>
+typedef void (*fp)(void);
+static fp every_entry[] = {
+    %s
+};
+int main(void) {
+    redsea_opts o = {REDSEA_VARIANT_RECURSIVE, 256, REDSEA_PREC_NATIVE, 0.0};
+    redsea_mixed_stats st;
+    memset(&st, 0, sizeof st);
+    (void)o;
+    printf("%%s %%s %%d\\n", redsea_version(), redsea_status_string(REDSEA_OK),
+           (int)(sizeof every_entry / sizeof every_entry[0]));
+    return 0;
+}
+""" % fns
+
+
+@pytest.mark.parametrize("compiler,std,ext", [("gcc", "-std=c11", "c"), ("g++", "-std=c++17", "cpp")])
+def test_header_compiles_standalone_and_links(tmp_path, compiler, std, ext):
+    """A C (or C++) client that includes only redsea.h builds warning-free,
+    takes the address of every declared entry point, links against
+    libredsea.so and runs (no device call)."""
+    src = tmp_path / ("consumer." + ext)
+    src.write_text(_consumer_source())
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(rs.LIB_PATH)
+    subprocess.run([compiler, std, "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", libdir, "-lredsea", "-Wl,-rpath," + libdir],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert out[0] == rs.version() and out[1] == "success"
+    assert int(out[2]) == len(_declared())

@@ -159,3 +159,58 @@ def test_run_to_run_bitwise_and_graph_replay():
         assert all(np.array_equal(b.cpu().numpy(), r) for b, r in zip(dBs, ref)), rep
         assert int(info.abs().sum().item()) == 0
     plan.close()
+
+
+def test_graph_replay_with_big_system_survives_larger_solve():
+    """A captured plan holding a system above order 1024 owns the memory of
+    that system's diagonal blocks: a larger redsea_trsm between replays (which
+    regrows the library's stream workspace) leaves every replay bitwise equal
+    to the eager run."""
+    As, Bs = _make(30, (3, 4, 2), n_range=(32, 400))
+    As.append(synth.dominant_lower(1500, (3, 97, 0)))
+    Bs.append(synth.rhs_normal(1500, 40, (3, 97, 1)))
+    dAs = [rs.fortran_tensor(a) for a in As]
+    dB0 = [rs.fortran_tensor(b) for b in Bs]
+    dBs = [b.clone() for b in dB0]
+    info = torch.zeros(len(Bs), dtype=torch.int32, device="cuda")
+    plan = rs.BatchPlan(dAs, dBs, variant="recursive", nb=256)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.run(info, stream=s)
+    torch.cuda.synchronize()
+    ref = [b.cpu().numpy() for b in dBs]
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, As[-1], Bs[-1], ref[-1]) <= 1e-14 * 1500
+    g = torch.cuda.CUDAGraph()
+    for b, b0 in zip(dBs, dB0):
+        b.copy_(b0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        plan.run(info, stream=s)
+    torch.cuda.synchronize()
+    big_L = rs.fortran_tensor(synth.dominant_lower(4000, (3, 96, 0)))
+    for rep in range(3):
+        # a larger solve on the same stream regrows its workspace
+        big_B = rs.fortran_tensor(synth.rhs_normal(4000, 64 * (rep + 1), (3, 96, 1)))
+        with torch.cuda.stream(s):
+            rs.trsm(big_L, big_B, variant="recursive", nb=256, stream=s)
+        torch.cuda.synchronize()
+        for b, b0 in zip(dBs, dB0):
+            b.copy_(b0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(np.array_equal(b.cpu().numpy(), r) for b, r in zip(dBs, ref)), rep
+    plan.close()
+
+
+def test_alpha_zero_overwrites_nonfinite_with_zero():
+    """BLAS semantics: alpha = 0 sets B to zero without reading it, so Inf and
+    NaN entries of B become 0, not NaN."""
+    As, Bs = _make(8, (3, 5, 2), n_range=(20, 200), nrhs_range=(1, 30))
+    for B in Bs:
+        B[0, 0] = np.inf
+        B[-1, -1] = np.nan
+    Xs, info = _run(As, Bs, alpha=0.0)
+    assert np.all(info == 0)
+    for X in Xs:
+        assert np.array_equal(X, np.zeros_like(X))

@@ -150,3 +150,67 @@ def test_mfma_peak_probe():
     f32 = rs.mfma_peak("f32", iters=512, reps=3)
     assert 10.0 < f64 < 100.0, f64
     assert f32 > 1.5 * f64, (f32, f64)
+
+
+def _round_bf16(x):
+    """FP32 -> BF16 by round-to-nearest-even on the bit pattern (finite
+    inputs), returned as float64 values."""
+    b = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _run_bf16(A, X, C, transa, transx):
+    """A holds BF16 values; X and C are FP32."""
+    dA = rs.fortran_tensor((A.T if transa else A).astype(np.float32)).to(torch.bfloat16)
+    dA = dA.t().contiguous().t()  # keep column-major storage after the cast
+    dX = rs.fortran_tensor((X.T if transx else X).astype(np.float32))
+    dC = rs.fortran_tensor((C.T if transx else C).astype(np.float32))
+    rs.gemm_update(dA, dX, dC, transa=transa, transx=transx)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy().astype(np.float64)
+    return out.T if transx else out
+
+
+def test_bf16_rounding_helper():
+    # ties go to even, and values already in BF16 are fixed points
+    one = np.float32(1.0).view(np.uint32)
+    half_ulp = np.array([one + 0x8000, one + 0x18000], np.uint32).view(np.float32)
+    got = _round_bf16(half_ulp)
+    assert got[0] == 1.0 and got[1] == 1.0 + 2.0 ** -6
+    v = np.array([0.5, -3.0, 2.0 ** -20, 1.0 + 2.0 ** -7], np.float32)
+    assert np.array_equal(_round_bf16(v), v.astype(np.float64))
+
+
+@pytest.mark.parametrize("transa,transx", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_bf16_product_elementwise(transa, transx):
+    """C := C - A RN_bf16(X) with FP32 accumulation, checked element by element
+    against an FP64 product of the same BF16 operands (exact products) within
+    the FP32 accumulation bound (K + 1) u32 (|C| + |A||X|)."""
+    for (M, N, K) in [(1, 1, 1), (37, 129, 5), (128, 128, 32), (200, 300, 150), (130, 70, 301),
+                      (515, 260, 1030)]:
+        r = synth.rng((34, M, N + K))
+        A = _round_bf16(r.standard_normal((M, K)))
+        X = r.standard_normal((K, N)).astype(np.float32).astype(np.float64)
+        C = r.standard_normal((M, N)).astype(np.float32).astype(np.float64)
+        got = _run_bf16(A, X, C, transa, transx)
+        Xb = _round_bf16(X)
+        ref = C - A @ Xb
+        bound = (K + 1) * U32 * (np.abs(C) + np.abs(A) @ np.abs(Xb))
+        err = np.abs(got - ref)
+        assert np.all(err <= bound), (M, N, K, float(np.max(err / np.maximum(bound, 1e-300))))
+        # rounding X matters: the unrounded product is farther away somewhere
+        if K >= 32:
+            assert np.max(np.abs(got - (C - A @ X))) > np.max(err)
+
+
+def test_bf16_product_integer_exact():
+    """Small integers are exact in BF16 and every FP32 partial sum is exact:
+    the result must equal the integer product bitwise."""
+    M, N, K = 300, 170, 257
+    r = synth.rng((35, 0, 0))
+    A = r.integers(-8, 9, (M, K)).astype(np.float64)
+    X = r.integers(-8, 9, (K, N)).astype(np.float64)
+    C = r.integers(-1000, 1000, (M, N)).astype(np.float64)
+    for transa, transx in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+        assert np.array_equal(_run_bf16(A, X, C, transa, transx), C - A @ X)

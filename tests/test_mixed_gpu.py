@@ -23,6 +23,18 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Corrections refinement needs on these workloads (measured on MI355X), so
+# a regression that stalls refinement and lets the FP64 fallback produce the
+# answer fails here instead of passing on the fallback's accuracy.
+ITER_MAX = {1: 2, 2: 4}
+
+
+def _refined(st, inner):
+    assert st.fell_back == 0, (inner, st.iterations, st.eta)
+    assert 1 <= st.iterations <= ITER_MAX[inner], (inner, st.iterations, st.eta)
+    assert st.eta <= 1e-12
+
+
 def mixed(A, B, inner, side=0, uplo=0, trans=0, diag=0, alpha=1.0, tol=0.0, max_iter=0):
     dA = rs.fortran_tensor(A)
     dB = rs.fortran_tensor(B)
@@ -52,6 +64,7 @@ def test_kappa_family_reaches_1e12(inner):
              % (target, inner, st.iterations, st.fell_back, st.eta, eta,
                 oracle.forward_error(X, Xo)))
         assert eta <= 1e-12, (target, eta)
+        _refined(st, inner)
 
 
 @pytest.mark.parametrize("inner", [1, 2])
@@ -78,6 +91,7 @@ def test_all_flags_backward_error(side, uplo, trans, diag):
         X, st = mixed(A, B, inner, side, uplo, trans, diag, alpha=-0.75)
         eta = oracle.backward_error(side, uplo, trans, diag, -0.75, A, B, X)
         assert eta <= 1e-12, (inner, eta, st.iterations, st.fell_back)
+        _refined(st, inner)
 
 
 @pytest.mark.parametrize("side,uplo,trans,diag", [(0, 0, 0, 0), (0, 1, 1, 0), (1, 0, 1, 1), (1, 1, 0, 0)])
@@ -93,6 +107,7 @@ def test_odd_sizes_backward_error(side, uplo, trans, diag):
         X, st = mixed(A, B, inner, side, uplo, trans, diag, alpha=1.5)
         eta = oracle.backward_error(side, uplo, trans, diag, 1.5, A, B, X)
         assert eta <= 1e-12, (inner, eta, st.iterations, st.fell_back)
+        _refined(st, inner)
 
 
 def test_unreachable_tolerance_falls_back_to_fp64():
@@ -131,11 +146,21 @@ def test_precision_option_of_trsm_routes_to_refinement():
     n, nrhs = 600, 50
     L = synth.kappa_lower(n, 0.05, (19, 0, 0))
     B = synth.rhs_normal(n, nrhs, (19, 0, 1))
-    for prec in ("fp32_ir", "bf16_ir"):
+    for prec, inner in (("fp32_ir", 1), ("bf16_ir", 2)):
         dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
-        rs.trsm(dL, dB, precision=prec)
+        rs.trsm(dL, dB, precision=prec, variant="recursive", nb=256)
         torch.cuda.synchronize()
-        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, dB.cpu().numpy()) <= 1e-12
+        X = dB.cpu().numpy()
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-12
+        # redsea_trsm_mixed with its defaults (recursive, nb 256, tol 1e-12)
+        # gives the same bits, and reports refinement, not the FP64 fallback
+        X2, st = mixed(L, B, inner)
+        assert np.array_equal(X, X2), prec
+        _refined(st, inner)
+        dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+        rs.trsm(dL, dB, precision="native", variant="recursive", nb=256)
+        torch.cuda.synchronize()
+        assert not np.array_equal(X, dB.cpu().numpy()), prec
 
 
 def test_larger_sampled():
@@ -151,3 +176,4 @@ def test_larger_sampled():
         eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, cols]), Xs)
         _say("n=8192 inner", inner, "iters", st.iterations, "fell_back", st.fell_back, "eta", eta)
         assert eta <= 1e-12
+        _refined(st, inner)

@@ -266,3 +266,69 @@ def test_column_groups_on_streams_bitwise(groups, monkeypatch):
     monkeypatch.setenv("REDSEA_STREAMS", groups)
     X2 = gpu_solve(L, Br, side=1, nb=64)
     assert np.array_equal(X1, X2)
+
+
+@pytest.mark.parametrize("k,nb", [(4096, 32), (6000, 32), (8192, 64)])
+def test_blocked_rounds_split_over_launches(k, nb):
+    """r = ceil(k / nb) >= 128 puts more blocks in a blocked round than one
+    grouped launch carries (48), so each round is split over launches."""
+    nrhs = 48
+    _say("blocked split", k, nb)
+    assert -(-k // nb) // 2 > 48
+    L = synth.dominant_lower(k, (21, k, 0))
+    B = synth.rhs_normal(k, nrhs, (21, k, 1))
+    X = gpu_solve(L, B, variant="blocked", nb=nb)
+    eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X)
+    assert eta <= 1e-14 * k, eta
+    assert oracle.forward_error(X, oracle.trsm_plain(0, 0, 0, 0, 1.0, L, B)) <= 1e-10
+
+
+def test_two_streams_concurrently_match_serial_bitwise():
+    """Two different solves in flight at once on two streams (each stream has
+    its own workspace) give exactly the bits of the same solves run one after
+    the other; the second stream's workspace grows while the first works."""
+    shapes = [(3000, 700, (22, 0)), (4100, 900, (22, 1))]
+    sysd = []
+    for k, nrhs, key in shapes:
+        L = synth.dominant_lower(k, key + (0,))
+        B = synth.rhs_normal(k, nrhs, key + (1,))
+        sysd.append((rs.fortran_tensor(L), rs.fortran_tensor(B)))
+    serial = []
+    for dL, dB0 in sysd:
+        dB = dB0.clone()
+        rs.trsm(dL, dB, variant="recursive", nb=256)
+        torch.cuda.synchronize()
+        serial.append(dB.cpu().numpy())
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        outs = [dB0.clone() for _, dB0 in sysd]
+        torch.cuda.synchronize()
+        for (dL, _), dB, st in zip(sysd, outs, streams):
+            rs.trsm(dL, dB, variant="recursive", nb=256, stream=st)
+        torch.cuda.synchronize()
+        for o, ref in zip(outs, serial):
+            assert np.array_equal(o.cpu().numpy(), ref), rep
+        streams.reverse()
+
+
+def test_graph_capture_is_refused_not_dangling():
+    """redsea_trsm on a stream under graph capture returns
+    REDSEA_ERR_UNSUPPORTED before launching anything; the library keeps
+    working afterwards."""
+    k, nrhs = 300, 20
+    L = synth.dominant_lower(k, (23, 0, 0))
+    B = synth.rhs_normal(k, nrhs, (23, 0, 1))
+    dL, dB = rs.fortran_tensor(L), rs.fortran_tensor(B)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    code = None
+    with torch.cuda.graph(g, stream=s):
+        try:
+            rs.trsm(dL, dB, variant="recursive", nb=128, stream=s)
+        except rs.RedseaError as e:
+            code = e.code
+    torch.cuda.synchronize()
+    assert code == 5
+    X = gpu_solve(L, B, variant="recursive", nb=128)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
