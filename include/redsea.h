@@ -102,7 +102,8 @@ enum {
     REDSEA_ERR_ALLOC = 2,
     REDSEA_ERR_NOCONV = 3,
     REDSEA_ERR_NONFINITE = 4,
-    REDSEA_ERR_UNSUPPORTED = 5
+    REDSEA_ERR_UNSUPPORTED = 5,
+    REDSEA_ERR_TOO_LARGE = 6 /* exceeds the fixed scratch of redsea_trsm_noalloc */
 };
 
 /*
@@ -125,6 +126,31 @@ enum {
 int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                 double alpha, const void* A, int64_t lda, void* B, int64_t ldb,
                 const redsea_opts* opts, void* stream);
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as redsea_trsm (same arguments, numbers and kernels; for a given
+ * variant and nb the result is bitwise that of redsea_trsm) in native
+ * precision only, with its scratch memory (the packed diagonal blocks) in a
+ * fixed device array of REDSEA_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each device it runs on until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine and never waits for the device, so it
+ * may be captured into a graph; the first call on a device looks up the
+ * array's address (hipGetSymbolAddress), so make one call there before
+ * capturing, an empty one (m = 0) will do.  variant AUTO means recursive, nb AUTO is 256
+ * above order 128, else 128 (no picker, no tuner); precision AUTO or NATIVE,
+ * and REDSEA_ERR_UNSUPPORTED for the refinement modes.  A problem whose
+ * packed diagonal blocks exceed the array (FP64 with nb 256: order above
+ * about 11000) returns REDSEA_ERR_TOO_LARGE before any device work.  Every
+ * call on one device shares that device's array: calls that overlap in time
+ * on one device (different streams, or several host threads) race and must
+ * be ordered by the caller.  Argument numbers as in redsea_trsm.
+ */
+#define REDSEA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int redsea_trsm_noalloc(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                        double alpha, const void* A, int64_t lda, void* B, int64_t ldb,
+                        const redsea_opts* opts, void* stream);
 
 /*
  * Variable-size batch of independent solves sharing flags and alpha

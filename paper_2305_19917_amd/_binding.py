@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libredsea.so")
 # Symbols the public header declares.
 EXPORTS = (
     "redsea_trsm",
+    "redsea_trsm_noalloc",
     "redsea_trsm_batched",
     "redsea_trsm_mixed",
     "redsea_trsm_mixed_workspace_bytes",
@@ -81,6 +82,8 @@ def lib() -> ctypes.CDLL:
     L.redsea_trsm.restype = cint
     L.redsea_trsm.argtypes = [cint, cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64,
                               ctypes.POINTER(Opts), ptr]
+    L.redsea_trsm_noalloc.restype = cint
+    L.redsea_trsm_noalloc.argtypes = L.redsea_trsm.argtypes
     L.redsea_trsm_batched.restype = cint
     L.redsea_trsm_batched.argtypes = [cint, cint, cint, cint, cint, i64, ctypes.POINTER(i64),
                                       ctypes.POINTER(i64), dbl, ctypes.POINTER(ptr),
@@ -191,6 +194,19 @@ def trsm(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
     rc = lib().redsea_trsm(_dtype_code(B), SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag],
                            m, n, float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
                            ctypes.byref(opts), _stream(stream))
+    _check(rc)
+    return B
+
+
+def trsm_noalloc(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
+                 variant="auto", nb: int = 0, stream=None):
+    """As trsm(), through redsea_trsm_noalloc: native precision, scratch in the
+    library's fixed device array, no allocation (graph-capturable)."""
+    m, n = B.shape
+    opts = Opts(VARIANT[variant], int(nb), PRECISION["native"])
+    rc = lib().redsea_trsm_noalloc(_dtype_code(B), SIDE[side], UPLO[uplo], TRANS[trans],
+                                   DIAG[diag], m, n, float(alpha), A.data_ptr(), _ld(A),
+                                   B.data_ptr(), _ld(B), ctypes.byref(opts), _stream(stream))
     _check(rc)
     return B
 

@@ -519,6 +519,7 @@ const char* redsea_status_string(int code) {
         case REDSEA_ERR_NOCONV: return "iterative refinement did not converge";
         case REDSEA_ERR_NONFINITE: return "non-finite value in result";
         case REDSEA_ERR_UNSUPPORTED: return "unsupported combination";
+        case REDSEA_ERR_TOO_LARGE: return "problem exceeds the fixed scratch memory";
         default: return "unknown status";
     }
 }
