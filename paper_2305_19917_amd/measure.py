@@ -13,6 +13,7 @@ Rows:
            kappa_1 in {1e2, 1e4, 1e6}: plain FP64 against FP32 + FP64 refinement
            and BF16 + FP64 refinement (effective TFLOP/s of the whole call,
            iterations and the library's own final backward error)
+  mixed1e4 the same at kappa_1 ~ 1e4 only, one timed repetition (for tracing)
   batched  2000 systems, n log-uniform in [32, 1024], nrhs in [1, 256], FP64
            and FP32, one plan launch (eager and hipGraph replay)
 
@@ -128,14 +129,23 @@ def row_thin():
         report("left lower N", nrhs, dL, ("L", "L", "N", "N"), 10)
 
 
-def row_mixed():
+# Constant-diagonal factors c of the kappa family at n = 16384 (matrix key
+# (2, 0, 0)) and the one-norm condition numbers they give, estimated with the
+# Hager-Higham estimator when the table of the family was made.
+KAPPA_FAMILY_16384 = ((1e2, 0.10366329284376985, 100.5), (1e4, 0.009821718891880384, 9608.0),
+                      (1e6, 0.0032196784442513815, 959245.0))
+
+
+def row_mixed(targets=(1e2, 1e4, 1e6), reps=3):
     import torch
     import paper_2305_19917_amd as rs
     import synth
-    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "kappa_family.json")))
     n, nrhs = 16384, 4096
-    for e in [x for x in tab["entries"] if x["n"] == n]:
-        L = synth.kappa_lower(n, e["c"], tuple(tab["key"]))
+    for target, c, kappa1 in KAPPA_FAMILY_16384:
+        if target not in targets:
+            continue
+        e = {"target": target, "kappa1": kappa1}
+        L = synth.kappa_lower(n, c, (2, 0, 0))
         B = synth.rhs_normal(n, nrhs, (2, 0, 1))
         dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
         dB = dB0.t().clone().t()
@@ -143,7 +153,7 @@ def row_mixed():
         for name, fn in (("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=256)),
                          ("fp32_ir", lambda: rs.trsm_mixed(dL, dB, inner=1)),
                          ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2))):
-            ms = _time(fn, lambda: dB.copy_(dB0), 3)
+            ms = _time(fn, lambda: dB.copy_(dB0), reps)
             dB.copy_(dB0)
             st = fn()
             torch.cuda.synchronize()
@@ -188,7 +198,7 @@ def row_batched():
 
 
 ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "mixed": row_mixed,
-        "batched": row_batched}
+        "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched}
 
 
 def main(argv):

@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kappa_family.json")
 N, NRHS = 16384, 4096
 COLS = [0, 1, 255, 256, 1023, 2048, 3071, 4095]
-ITER_MAX = {1: 2, 2: 4}
+ITER_MAX = {1: 1, 2: 3}
 
 
 def _say(*a):
