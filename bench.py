@@ -152,7 +152,13 @@ def mixed_leg(n, nrhs, reps, log):
            "reps": reps, "sampled_columns": cols}
     legs = [("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=256, stream=stream)),
             ("fp32_ir", lambda: rs.trsm_mixed(dL, dB, inner=1, stream=stream)),
-            ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2, stream=stream))]
+            ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2, stream=stream)),
+            # labelled variants: the residual by exact integer emulation on the
+            # INT8 matrix cores (Ozaki scheme II) instead of FP64 products
+            ("fp32_ir_int8res", lambda: rs.trsm_mixed(dL, dB, inner=1 | rs.RESIDUAL_INT8,
+                                                      stream=stream)),
+            ("bf16_ir_int8res", lambda: rs.trsm_mixed(dL, dB, inner=2 | rs.RESIDUAL_INT8,
+                                                      stream=stream))]
     for name, call in legs:
         log("mixed leg: %s" % name)
         ms, st = timed(call)
@@ -162,7 +168,7 @@ def mixed_leg(n, nrhs, reps, log):
         if name != "fp64":
             rec.update(iterations=st.iterations, fell_back=st.fell_back, eta_library=st.eta)
         out[name] = rec
-    for name in ("fp32_ir", "bf16_ir"):
+    for name in ("fp32_ir", "bf16_ir", "fp32_ir_int8res", "bf16_ir_int8res"):
         out[name]["speed_vs_fp64"] = round(out["fp64"]["ms"] / out[name]["ms"], 4)
     return out
 

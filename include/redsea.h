@@ -196,6 +196,33 @@ int redsea_batched_plan_create(int dtype, int side, int uplo, int trans, int dia
 int redsea_batched_plan_run(redsea_batch_plan* plan, int* info, void* stream);
 void redsea_batched_plan_destroy(redsea_batch_plan* plan);
 
+/*
+ * Triangular matrix product (BLAS xTRMM extended to an output operand):
+ *     side = REDSEA_LEFT :  C := beta C + alpha op(A) B      (A is m x m)
+ *     side = REDSEA_RIGHT:  C := beta C + alpha B op(A)      (A is n x n)
+ * with B and C m x n (they must not overlap), A triangular (only its uplo
+ * triangle is read; a unit diagonal is never read), C not read when beta is
+ * 0.  It is the product the update stage of the split (Sec. IV) performs
+ * when the whole triangle multiplies, and with beta = alpha_b, alpha = -1,
+ * B = X it is the residual alpha_b B - op(A) X of a solve.  method
+ * REDSEA_TRMM_MFMA: products on the matrix cores in dtype (FP64 or FP32),
+ * only the tiles that meet the triangle.  method REDSEA_TRMM_INT8 (FP64
+ * only): the product is emulated exactly in integer arithmetic (Ozaki scheme
+ * II: rows of op(A) and columns of B rounded to 53-bit integers after
+ * power-of-two scaling, 16 modular products on the INT8 matrix cores,
+ * Chinese-remainder reconstruction), so its error is that of rounding each
+ * row / column to 53 bits relative to its largest entry -- the accuracy of an
+ * FP64 product, not FP64 arithmetic.  Workspace (INT8 method: about
+ * 16 (k^2 + 2 k nrhs) bytes, k the order of A) comes from the per-stream
+ * buffer described at redsea_trsm.  Argument numbers: dtype 1, side 2, uplo 3,
+ * trans 4, diag 5, m 6, n 7, alpha 8, A 9, lda 10, B 11, ldb 12, beta 13,
+ * C 14, ldc 15, method 16, stream 17.
+ */
+enum { REDSEA_TRMM_MFMA = 0, REDSEA_TRMM_INT8 = 1 };
+int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                double beta, void* C, int64_t ldc, int method, void* stream);
+
 /* Statistics of one mixed-precision solve (host struct). */
 typedef struct {
     int iterations; /* refinement corrections applied            */
@@ -206,19 +233,25 @@ typedef struct {
 /*
  * FP64 solve computed with low-precision inner solves and FP64 iterative
  * refinement (spec precision pattern): X0 from an FP32 (inner = 1) or
- * BF16-product (inner = 2) solve, then repeated R = alpha B - op(A) X in FP64,
+ * BF16-product (inner = 2) solve, then repeated R = alpha B - op(A) X in FP64
+ * (with inner | REDSEA_RESIDUAL_INT8: by the exact integer emulation of
+ * redsea_trmm's REDSEA_TRMM_INT8 method, a labelled variant),
  * a low-precision correction solve and X += D in FP64, until the normwise
  * backward error is at most tol (tol <= 0 means 1e-12) or max_iter
  * (<= 0: 5 for FP32, 10 for BF16) is reached; on stagnation or no
- * convergence it falls back to the FP64 solve.  inner = 0 picks
- * automatically.  work/work_bytes: optional DEVICE workspace of at least
- * redsea_trsm_mixed_workspace_bytes(...) bytes; NULL uses the library's
- * per-(device, stream) buffer as redsea_trsm does.  stats: optional HOST struct.  This call synchronizes the stream
- * once per refinement step to read the convergence test.  Argument numbers:
+ * convergence it falls back to the FP64 solve.  inner = 0 (or a bare
+ * REDSEA_RESIDUAL_INT8) means FP32; any other value returns -12.
+ * work/work_bytes: optional DEVICE workspace of at least
+ * redsea_trsm_mixed_workspace_bytes(side, m, n, inner) bytes (the same inner
+ * code, flag included); NULL uses the library's per-(device, stream) buffer
+ * as redsea_trsm does.  stats: optional HOST struct.  This call synchronizes
+ * the stream once per refinement step to read the convergence test.
+ * Argument numbers:
  * side 1, uplo 2, trans 3, diag 4, m 5, n 6, alpha 7, A 8, lda 9, B 10,
  * ldb 11, inner 12, tol 13, max_iter 14, work 15, work_bytes 16, stats 17,
  * stream 18.
  */
+enum { REDSEA_RESIDUAL_INT8 = 16 };
 int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                       double alpha, const double* A, int64_t lda, double* B, int64_t ldb,
                       int inner, double tol, int max_iter, void* work, size_t work_bytes,

@@ -20,6 +20,7 @@ EXPORTS = (
     "redsea_trsm_noalloc",
     "redsea_trsm_batched",
     "redsea_trsm_mixed",
+    "redsea_trmm",
     "redsea_trsm_mixed_workspace_bytes",
     "redsea_status_string",
     "redsea_schedule",
@@ -92,6 +93,9 @@ def lib() -> ctypes.CDLL:
     L.redsea_trsm_mixed.restype = cint
     L.redsea_trsm_mixed.argtypes = [cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64,
                                     cint, dbl, cint, ptr, sz, ctypes.POINTER(MixedStats), ptr]
+    L.redsea_trmm.restype = cint
+    L.redsea_trmm.argtypes = [cint, cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64, dbl,
+                              ptr, i64, cint, ptr]
     L.redsea_trsm_mixed_workspace_bytes.restype = sz
     L.redsea_trsm_mixed_workspace_bytes.argtypes = [cint, i64, i64, cint]
     L.redsea_status_string.restype = ctypes.c_char_p
@@ -287,6 +291,23 @@ def trsm_mixed(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0
                                  ctypes.byref(st), _stream(stream))
     _check(rc)
     return st
+
+
+TRMM_METHOD = {"mfma": 0, "int8": 1, 0: 0, 1: 1}
+RESIDUAL_INT8 = 16
+
+
+def trmm(A, B, C, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
+         beta: float = 0.0, method="mfma", stream=None):
+    """C := beta C + alpha op(A) B (side L) or beta C + alpha B op(A) (side R),
+    A triangular; method "int8" is the exact integer emulation (FP64 only).
+    Returns C."""
+    m, n = C.shape
+    rc = lib().redsea_trmm(_dtype_code(C), SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag], m, n,
+                           float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), float(beta),
+                           C.data_ptr(), _ld(C), TRMM_METHOD[method], _stream(stream))
+    _check(rc)
+    return C
 
 
 def gemm_update(A, X, C, transa=False, transx=False, tile: int = -1, stream=None):

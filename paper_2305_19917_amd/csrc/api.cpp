@@ -17,6 +17,7 @@
 #include "exec.h"
 #include "kernels.h"
 #include "mixed.h"
+#include "ozaki.h"
 #include "picker.h"
 #include "plan.h"
 
@@ -137,17 +138,19 @@ GemmArgs gemm_args(const Canon& c, int64_t r0, int64_t R, int64_t c0, int64_t K)
     }
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
     GemmArgs g;
-    if (c.gemm_bf16) {
-        const char* a16 = (const char*)c.A16;
-        g.a = c.op_trans ? a16 + 2 * (K0 + R0 * c.lda) : a16 + 2 * (R0 + K0 * c.lda);
-    }
     g.M = R;
     g.N = c.nrhs;
     g.K = K;
     const char* a = (const char*)c.A;
-    // M(i, j) = A[i + j*lda] (not transposed) or A[j + i*lda] (transposed)
-    if (!c.gemm_bf16) g.a = c.op_trans ? a + es * (K0 + R0 * c.lda) : a + es * (R0 + K0 * c.lda);
-    g.lda = c.lda;
+    // M(i, j) = A[i + j*lda] (not transposed) or A[j + i*lda] (transposed);
+    // the BF16 copy holds M by rows
+    if (c.gemm_bf16) {
+        g.a = (const char*)c.A16 + 2 * (K0 + R0 * c.lda16);
+        g.lda = c.lda16;
+    } else {
+        g.a = c.op_trans ? a + es * (K0 + R0 * c.lda) : a + es * (R0 + K0 * c.lda);
+        g.lda = c.lda;
+    }
     char* b = (char*)c.B;
     if (!c.rhs_trans) {
         g.x = b + es * K0;
@@ -309,7 +312,7 @@ int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, con
                                        tasks[q].cols);
                 const double fl = 2.0 * g.M * g.N * g.K;
                 if (traced(REDSEA_KERNEL_GEMM, fl, s, [&] {
-                        return launch_gemm_bf16(c.op_trans, c.rhs_trans, g, s);
+                        return launch_gemm_bf16(true, c.rhs_trans, g, s);
                     }) != hipSuccess)
                     return REDSEA_ERR_HIP;
             }
@@ -590,6 +593,58 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
     Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb);
     if (variant == 0) variant = VAR_RECURSIVE;
     return execute(c, variant, pick_nb(nb, c.k), s);
+}
+
+int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                double beta, void* C, int64_t ldc, int method, void* stream) {
+    if (dtype != REDSEA_F64 && dtype != REDSEA_F32) return -1;
+    if (side != REDSEA_LEFT && side != REDSEA_RIGHT) return -2;
+    if (uplo != REDSEA_LOWER && uplo != REDSEA_UPPER) return -3;
+    if (trans != REDSEA_NOTRANS && trans != REDSEA_TRANS && trans != REDSEA_CONJTRANS) return -4;
+    if (diag != REDSEA_NONUNIT && diag != REDSEA_UNIT) return -5;
+    if (m < 0) return -6;
+    if (n < 0) return -7;
+    const int64_t ka = side == REDSEA_LEFT ? m : n;
+    if (lda < std::max<int64_t>(1, ka)) return -10;
+    if (ldb < std::max<int64_t>(1, m)) return -12;
+    if (ldc < std::max<int64_t>(1, m)) return -15;
+    if (method != REDSEA_TRMM_MFMA && method != REDSEA_TRMM_INT8) return -16;
+    if (method == REDSEA_TRMM_INT8 && dtype != REDSEA_F64) return -16;
+    if (m == 0 || n == 0) return REDSEA_OK;
+    if (alpha != 0.0) {
+        if (!A) return -9;
+        if (!B) return -11;
+    }
+    if (!C) return -14;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0)  // C := beta C (zeros without reading C when beta is 0)
+        return beta == 1.0 || launch_scale(dtype, C, m, n, ldc, beta, s) == hipSuccess
+                   ? REDSEA_OK
+                   : REDSEA_ERR_HIP;
+    // the product in storage coordinates: C (left) or C^T (right) += M X with
+    // M = op(A) (left) or op(A)^T (right)
+    const bool right = side == REDSEA_RIGHT;
+    const bool a_trans = right ? trans == REDSEA_NOTRANS : trans != REDSEA_NOTRANS;
+    const int tri = ((uplo == REDSEA_LOWER) != a_trans) ? 1 : 2;
+    const bool unit = diag == REDSEA_UNIT;
+    const int64_t k = ka, nrhs = right ? m : n;
+    if (method == REDSEA_TRMM_INT8) {
+        WsLease lease;
+        const size_t mb = (ozaki_m_bytes(k) + 255) & ~(size_t)255;
+        int rc = workspace(5, mb + ozaki_x_bytes(k, nrhs), s, lease);
+        if (rc) return rc;
+        char* ws = (char*)lease.ptr;
+        if (ozaki_split_m((const double*)A, lda, k, uplo, a_trans, unit, ws, s) != hipSuccess ||
+            ozaki_product(ws, tri, k, nrhs, right, beta, alpha, (const double*)B, ldb,
+                          (const double*)C, ldc, (double*)C, ldc, ws + mb, s) != hipSuccess)
+            return REDSEA_ERR_HIP;
+        return REDSEA_OK;
+    }
+    GemmArgs g{k, nrhs, k, A, lda, B, ldb, C, ldc};
+    return launch_trmm(dtype, a_trans, right, tri, unit, beta, alpha, g, s) == hipSuccess
+               ? REDSEA_OK
+               : REDSEA_ERR_HIP;
 }
 
 void redsea_trace_begin(void) {

@@ -27,11 +27,12 @@ struct Canon {
     int64_t ldb;
     TriView tri;
     RhsView rhs;
-    // BF16 products (mixed precision): the products read the BF16 copy A16
-    // (same layout and leading dimension as A, which then is FP32) and round
-    // X to BF16 on load; leaves stay on A.
+    // BF16 products (mixed precision): the products read the BF16 copy A16 of
+    // M = op_eff(A) stored by rows (M(i, j) at A16[j + i*lda16]) and round X
+    // to BF16 as they read it; leaves stay on A (FP32).
     bool gemm_bf16 = false;
     const void* A16 = nullptr;
+    int64_t lda16 = 0;
 };
 
 Canon canonicalize(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tiles.h"
 
 namespace redsea {
 
@@ -121,7 +122,7 @@ __device__ __forceinline__ void store_stage(Smem<T, C>& sm, int buf, int tid, co
 
 template <typename T, typename C, bool AT, bool RT, int TRI = 0, bool UNIT = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
-                                          Smem<T, C>& sm, T alpha_c = T(1)) {
+                                          Smem<T, C>& sm, T beta = T(1), T gamma = T(-1)) {
     typedef typename Mfma<T>::acc_t acc_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % C::WM, wn = wave / C::WM;
@@ -178,28 +179,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
                 const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
                 if (gi < g.M && gj < g.N) {
                     T* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    *p = (TRI == 0 ? *p : alpha_c * *p) - acc[i][j][r];
+                    if (TRI == 0) *p = *p - acc[i][j][r];
+                    else *p = (beta == T(0) ? T(0) : beta * *p) + gamma * acc[i][j][r];
                 }
             }
-}
-
-// Workgroups are dispatched round-robin over the eight XCDs (each with its
-// own L2).  The launch index is remapped so that every XCD receives one
-// contiguous range of logical tiles, and logical tiles walk bands of GM
-// row-tiles along N, so an XCD's resident workgroups share A row panels and
-// X column panels in its L2.
-__device__ __forceinline__ void tile_coords(int64_t tiles_m, int64_t tiles_n, int64_t& tm,
-                                            int64_t& tn) {
-    constexpr int64_t kXcd = 8, GM = 8;
-    const int64_t nwg = (int64_t)gridDim.x;
-    int64_t bid = blockIdx.x;
-    if (nwg % kXcd == 0) bid = (bid % kXcd) * (nwg / kXcd) + bid / kXcd;
-    const int64_t band = GM * tiles_n;
-    const int64_t first = (bid / band) * GM;
-    const int64_t gsz = tiles_m - first < GM ? tiles_m - first : GM;
-    const int64_t r = bid % band;
-    tm = first + r % gsz;
-    tn = r / gsz;
 }
 
 template <typename T, typename C, bool AT, bool RT>
@@ -484,7 +467,8 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
 
 // TRI = 0: C -= A X.  TRI = 1 / 2: A is the lower / upper triangle of its
 // storage (the other triangle is never used, whatever it holds; with UNIT the
-// diagonal is taken as 1) and C := alpha_c C - A X, the residual of a
+// diagonal is taken as 1) and C := beta C + gamma A X (C not read when beta
+// is 0): the triangular product, and with gamma = -1 the residual of a
 // triangular solve.  Only the k-stages that meet the triangle in rows
 // [m0, m0 + BM) are run, and in the stages that cross the diagonal the A
 // fragments are masked after they are read from LDS.
@@ -492,7 +476,8 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
 // dimension) instead of 16-byte ones (even shapes and leading dimensions).
 template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false,
           bool DW = false>
-__global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g, double alpha_c) {
+__global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g, double beta,
+                                                                      double gamma) {
     typedef DmaCfg<BM, BN, WM, WN, MINB, AT, RT> D;
     __shared__ __attribute__((aligned(1024))) char smem[2 * D::STAGE];
     const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
@@ -608,7 +593,8 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
                 const int64_t gj = n0 + wn * D::SN + j * 16 + (lane & 15);
                 if (gi < g.M && gj < g.N) {
                     double* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    *p = (TRI == 0 ? *p : alpha_c * *p) - acc[i][j][r];
+                    if (TRI == 0) *p = *p - acc[i][j][r];
+                    else *p = (beta == 0.0 ? 0.0 : beta * *p) + gamma * acc[i][j][r];
                 }
             }
 }
@@ -638,27 +624,28 @@ bool dma_ok(const GemmArgs& g) {
 
 template <int BM, int BN, int WM, int WN, int MINB, bool AT, bool RT, int TRI = 0, bool UNIT = false,
           bool DW = false>
-hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s, double alpha_c = 1.0) {
+hipError_t gemm_dma_launch_f64(const GemmArgs& g, hipStream_t s, double beta = 1.0,
+                               double gamma = -1.0) {
     const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     hipLaunchKernelGGL((gemm_dma_kernel<BM, BN, WM, WN, MINB, AT, RT, TRI, UNIT, DW>),
-                       dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, alpha_c);
+                       dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, beta, gamma);
     return hipGetLastError();
 }
 
-template <typename C, bool AT, bool RT, int TRI, bool UNIT>
-__global__ __launch_bounds__(C::NT, C::MINB) void residual_kernel(GemmArgs g, double alpha) {
-    __shared__ Smem<double, C> sm;
+template <typename T, typename C, bool AT, bool RT, int TRI, bool UNIT>
+__global__ __launch_bounds__(C::NT, C::MINB) void residual_kernel(GemmArgs g, T beta, T gamma) {
+    __shared__ Smem<T, C> sm;
     const int64_t tiles_m = (g.M + C::BM - 1) / C::BM, tiles_n = (g.N + C::BN - 1) / C::BN;
     int64_t tm, tn;
     tile_coords(tiles_m, tiles_n, tm, tn);
-    gemm_tile<double, C, AT, RT, TRI, UNIT>(g, tm * C::BM, tn * C::BN, sm, alpha);
+    gemm_tile<T, C, AT, RT, TRI, UNIT>(g, tm * C::BM, tn * C::BN, sm, beta, gamma);
 }
 
-template <typename C, bool AT, bool RT, int TRI, bool UNIT>
-hipError_t residual_launch(const GemmArgs& g, double alpha, hipStream_t s) {
+template <typename T, typename C, bool AT, bool RT, int TRI, bool UNIT>
+hipError_t residual_launch(const GemmArgs& g, double beta, double gamma, hipStream_t s) {
     const int64_t tiles = ((g.M + C::BM - 1) / C::BM) * ((g.N + C::BN - 1) / C::BN);
-    hipLaunchKernelGGL((residual_kernel<C, AT, RT, TRI, UNIT>), dim3((unsigned)tiles), dim3(C::NT),
-                       0, s, g, alpha);
+    hipLaunchKernelGGL((residual_kernel<T, C, AT, RT, TRI, UNIT>), dim3((unsigned)tiles),
+                       dim3(C::NT), 0, s, g, (T)beta, (T)gamma);
     return hipGetLastError();
 }
 
@@ -771,35 +758,41 @@ hipError_t gemm_group_any(int tile, bool at, bool rt, const GemmGroup& grp, hipS
     return gemm_group_by_tile<T, true, true>(tile, grp, s);
 }
 
-template <bool AT, bool RT, int TRI>
-hipError_t residual_u(bool unit, const GemmArgs& g, double alpha, hipStream_t s) {
-    // direct-to-LDS 128 x 128 tile on eight waves where the shape allows it
-    if (dma_ok<128, 128, AT, RT>(g))
-        return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true>(g, s, alpha)
-                    : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false>(g, s, alpha);
-    if (dma_span_ok<128, 128, AT, RT>(g))
-        return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true, true>(g, s, alpha)
-                    : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false, true>(g, s, alpha);
-    return unit ? residual_launch<Tile5, AT, RT, TRI, true>(g, alpha, s)
-                : residual_launch<Tile5, AT, RT, TRI, false>(g, alpha, s);
+template <typename T, bool AT, bool RT, int TRI>
+hipError_t residual_u(bool unit, const GemmArgs& g, double beta, double gamma, hipStream_t s) {
+    // FP64: direct-to-LDS 128 x 128 tile on eight waves where the shape allows it
+    if constexpr (sizeof(T) == 8) {
+        if (dma_ok<128, 128, AT, RT>(g))
+            return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true>(g, s, beta, gamma)
+                        : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false>(g, s, beta, gamma);
+        if (dma_span_ok<128, 128, AT, RT>(g))
+            return unit ? gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, true, true>(g, s, beta, gamma)
+                        : gemm_dma_launch_f64<128, 128, 4, 2, 2, AT, RT, TRI, false, true>(g, s, beta, gamma);
+    }
+    return unit ? residual_launch<T, Tile5, AT, RT, TRI, true>(g, beta, gamma, s)
+                : residual_launch<T, Tile5, AT, RT, TRI, false>(g, beta, gamma, s);
 }
 
-template <int TRI>
-hipError_t residual_t(bool at, bool rt, bool unit, const GemmArgs& g, double alpha, hipStream_t s) {
-    if (!at && !rt) return residual_u<false, false, TRI>(unit, g, alpha, s);
-    if (at && !rt) return residual_u<true, false, TRI>(unit, g, alpha, s);
-    if (!at && rt) return residual_u<false, true, TRI>(unit, g, alpha, s);
-    return residual_u<true, true, TRI>(unit, g, alpha, s);
+template <typename T, int TRI>
+hipError_t residual_t(bool at, bool rt, bool unit, const GemmArgs& g, double beta, double gamma,
+                      hipStream_t s) {
+    if (!at && !rt) return residual_u<T, false, false, TRI>(unit, g, beta, gamma, s);
+    if (at && !rt) return residual_u<T, true, false, TRI>(unit, g, beta, gamma, s);
+    if (!at && rt) return residual_u<T, false, true, TRI>(unit, g, beta, gamma, s);
+    return residual_u<T, true, true, TRI>(unit, g, beta, gamma, s);
 }
 
 }  // namespace
 
-hipError_t launch_residual(bool a_trans, bool rhs_trans, int tri, bool unit, double alpha,
-                           const GemmArgs& g, hipStream_t s) {
+hipError_t launch_trmm(int dtype, bool a_trans, bool rhs_trans, int tri, bool unit, double beta,
+                       double gamma, const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    if (tri == 1) return residual_t<1>(a_trans, rhs_trans, unit, g, alpha, s);
-    if (tri == 2) return residual_t<2>(a_trans, rhs_trans, unit, g, alpha, s);
-    return hipErrorInvalidValue;
+    if (tri != 1 && tri != 2) return hipErrorInvalidValue;
+    if (dtype == 0)
+        return tri == 1 ? residual_t<double, 1>(a_trans, rhs_trans, unit, g, beta, gamma, s)
+                        : residual_t<double, 2>(a_trans, rhs_trans, unit, g, beta, gamma, s);
+    return tri == 1 ? residual_t<float, 1>(a_trans, rhs_trans, unit, g, beta, gamma, s)
+                    : residual_t<float, 2>(a_trans, rhs_trans, unit, g, beta, gamma, s);
 }
 
 int gemm_tile_count() { return kTiles; }

@@ -56,12 +56,14 @@ struct GemmArgs {
     int64_t ldc;
 };
 
-// Residual product R := alpha * R - M X with M the k x k triangle of the
+// Triangular product C := beta C + gamma M X with M the k x k triangle of the
 // library's storage coordinates: M(i, j) = a[i + j*lda] (a_trans false) or
 // a[j + i*lda]; lower (tri = 1) or upper (tri = 2) part only, unit diagonal
-// taken as one and not read.  FP64 only.  M = N rows/cols of the args.
-hipError_t launch_residual(bool a_trans, bool rhs_trans, int tri, bool unit, double alpha,
-                           const GemmArgs& g, hipStream_t s);
+// taken as one and not read; C is not read when beta is 0.  dtype 0 (FP64)
+// or 1 (FP32).  M = N rows/cols of the args; X and C as in a product update.
+// With gamma = -1 this is the residual R = beta B - M X of a solve.
+hipError_t launch_trmm(int dtype, bool a_trans, bool rhs_trans, int tri, bool unit, double beta,
+                       double gamma, const GemmArgs& g, hipStream_t s);
 // tile < 0 picks the default tile configuration for the shape.
 hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s,
                        int tile = -1);

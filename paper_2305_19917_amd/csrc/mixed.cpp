@@ -26,18 +26,25 @@
 #include "exec.h"
 #include "kernels.h"
 #include "mixed.h"
+#include "ozaki.h"
 
 namespace redsea {
 
 namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+// Leading dimensions of the low-precision working copies: the BF16 matrix is
+// stored by rows padded to 8 elements and the FP32 right-hand sides by columns
+// padded to 4, so rows / columns start on 16-byte boundaries (the BF16
+// product's 16-byte operand loads).
+int64_t ld16(int64_t k) { return (k + 7) / 8 * 8; }
+int64_t ldw(int64_t m) { return (m + 3) / 4 * 4; }
 
 struct MixedLayout {
-    size_t a32, a16, b0, r, w32, rnorm, xnorm, bnorm, scal, rowsum, total;
+    size_t a32, a16, b0, r, w32, rnorm, xnorm, bnorm, scal, rowsum, ozm, ozx, total;
 };
 
-MixedLayout layout(int64_t m, int64_t n, int64_t k, int64_t nrhs, bool bf16) {
+MixedLayout layout(int64_t m, int64_t n, int64_t k, int64_t nrhs, bool bf16, bool ozaki) {
     MixedLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -46,15 +53,17 @@ MixedLayout layout(int64_t m, int64_t n, int64_t k, int64_t nrhs, bool bf16) {
         return o;
     };
     L.a32 = take((size_t)k * k * 4);
-    L.a16 = take(bf16 ? (size_t)k * k * 2 : 0);
+    L.a16 = take(bf16 ? (size_t)k * ld16(k) * 2 : 0);
     L.b0 = take((size_t)m * n * 8);
     L.r = take((size_t)m * n * 8);
-    L.w32 = take((size_t)m * n * 4);
+    L.w32 = take((size_t)ldw(m) * n * 4);
     L.rnorm = take((size_t)nrhs * 8);
     L.xnorm = take((size_t)nrhs * 8);
     L.bnorm = take((size_t)nrhs * 8);
     L.scal = take((size_t)nrhs * 8);
     L.rowsum = take((size_t)k * 8);
+    L.ozm = take(ozaki ? ozaki_m_bytes(k) : 0);
+    L.ozx = take(ozaki ? ozaki_x_bytes(k, nrhs) : 0);
     L.total = off;
     return L;
 }
@@ -109,12 +118,13 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
                 const double* A, int64_t lda, double* B, int64_t ldb, int inner, double tol,
                 int max_iter, void* work, size_t work_bytes, redsea_mixed_stats* stats,
                 const redsea_opts* opts, hipStream_t s) {
-    const bool bf16 = inner == 2;
+    const bool bf16 = (inner & 3) == 2;
+    const bool ozaki = (inner & REDSEA_RESIDUAL_INT8) != 0;
     const bool right = side == REDSEA_RIGHT;
     const Canon c64 = canonicalize(REDSEA_F64, side, uplo, trans, diag, m, n, A, lda, B, ldb);
     const int64_t k = c64.k, nrhs = c64.nrhs;
     const bool unit = diag == REDSEA_UNIT;
-    const MixedLayout L = layout(m, n, k, nrhs, bf16);
+    const MixedLayout L = layout(m, n, k, nrhs, bf16, ozaki);
     char* ws = (char*)work;
     WsLease lease;
     if (ws) {
@@ -134,6 +144,8 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     double* bnorm = (double*)(ws + L.bnorm);
     double* scal = (double*)(ws + L.scal);
     double* rowsum = (double*)(ws + L.rowsum);
+    void* ozm = ws + L.ozm;
+    void* ozx = ws + L.ozx;
     double* host = nullptr;
     std::unique_lock<std::mutex> pin_lock;
     int rc = pinned((size_t)3 * nrhs + (size_t)k, s, pin_lock, &host);
@@ -149,7 +161,9 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
 
     // low-precision copies of the triangle, FP64 copy of B, norms of op(A), alpha B
     HIPCHK(launch_convert_tri(0, A, lda, k, uplo, unit, a32, s));
-    if (bf16) HIPCHK(launch_convert_tri(1, A, lda, k, uplo, unit, a16, s));
+    if (bf16) HIPCHK(launch_convert_rows_bf16(A, lda, k, uplo, unit, c64.op_trans, a16, ld16(k), s));
+    // integer residue planes of op(A) for the emulated residual
+    if (ozaki) HIPCHK(ozaki_split_m(A, lda, k, uplo, c64.op_trans, unit, ozm, s));
     HIPCHK(launch_copy_scaled(B, ldb, m, n, 1.0, b0, m, s));
     HIPCHK(launch_tri_rowsum(A, lda, k, c64.op_trans, m_lower, unit, rowsum, s));
     HIPCHK(launch_rhs_max(b0, m, m, n, right, std::fabs(alpha), bnorm, s));
@@ -161,25 +175,32 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
     std::vector<double> bn(h_aux, h_aux + nrhs);
 
     auto low_solve = [&]() -> int {
-        Canon c32 = canonicalize(REDSEA_F32, side, uplo, trans, diag, m, n, a32, k, w32, m);
+        Canon c32 = canonicalize(REDSEA_F32, side, uplo, trans, diag, m, n, a32, k, w32, ldw(m));
         c32.gemm_bf16 = bf16;
         c32.A16 = a16;
+        c32.lda16 = ld16(k);
         return execute(c32, variant, nb, s);
     };
 
     // X0
-    HIPCHK(launch_scale_to_f32(b0, m, m, n, nullptr, right, alpha, w32, m, s));
+    HIPCHK(launch_scale_to_f32(b0, m, m, n, nullptr, right, alpha, w32, ldw(m), s));
     if ((rc = low_solve())) return rc;
-    HIPCHK(launch_update(B, ldb, m, n, w32, m, nullptr, right, false, s));
+    HIPCHK(launch_update(B, ldb, m, n, w32, ldw(m), nullptr, right, false, s));
 
     const GemmArgs rg{k, nrhs, k, A, lda, B, ldb, r, m};
     double eta = INFINITY, prev = INFINITY;
     int iters = 0;
     bool fell_back = false;
     for (;;) {
-        // R = alpha B0 - op(A) X in FP64
-        HIPCHK(launch_copy_scaled(b0, m, m, n, 1.0, r, m, s));
-        HIPCHK(launch_residual(c64.op_trans, right, m_lower ? 1 : 2, unit, alpha, rg, s));
+        // R = alpha B0 - op(A) X: FP64 products, or the exact integer
+        // emulation (as accurate as an FP64 product)
+        if (ozaki) {
+            HIPCHK(ozaki_product(ozm, m_lower ? 1 : 2, k, nrhs, right, alpha, -1.0, B, ldb, b0, m,
+                                 r, m, ozx, s));
+        } else {
+            HIPCHK(launch_copy_scaled(b0, m, m, n, 1.0, r, m, s));
+            HIPCHK(launch_trmm(0, c64.op_trans, right, m_lower ? 1 : 2, unit, alpha, -1.0, rg, s));
+        }
         HIPCHK(launch_rhs_max(r, m, m, n, right, 1.0, rnorm, s));
         HIPCHK(launch_rhs_max(B, ldb, m, n, right, 1.0, xnorm, s));
         HIPCHK(hipMemcpyAsync(h_r, rnorm, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s));
@@ -201,9 +222,9 @@ int mixed_solve(int side, int uplo, int trans, int diag, int64_t m, int64_t n, d
         // D = low solve of R / ||R||, X += ||R|| D
         for (int64_t j = 0; j < nrhs; ++j) h_aux[j] = h_r[j] > 0 ? 1.0 / h_r[j] : 0.0;
         HIPCHK(hipMemcpyAsync(scal, h_aux, (size_t)nrhs * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_scale_to_f32(r, m, m, n, scal, right, 1.0, w32, m, s));
+        HIPCHK(launch_scale_to_f32(r, m, m, n, scal, right, 1.0, w32, ldw(m), s));
         if ((rc = low_solve())) return rc;
-        HIPCHK(launch_update(B, ldb, m, n, w32, m, rnorm, right, true, s));
+        HIPCHK(launch_update(B, ldb, m, n, w32, ldw(m), rnorm, right, true, s));
         ++iters;
     }
     if (fell_back) {
@@ -224,7 +245,7 @@ size_t mixed_workspace_bytes(int side, int64_t m, int64_t n, int inner) {
     if (m <= 0 || n <= 0) return 0;
     const int64_t k = side == REDSEA_RIGHT ? n : m;
     const int64_t nrhs = side == REDSEA_RIGHT ? m : n;
-    return layout(m, n, k, nrhs, inner == 2).total;
+    return layout(m, n, k, nrhs, (inner & 3) == 2, (inner & REDSEA_RESIDUAL_INT8) != 0).total;
 }
 
 }  // namespace redsea
@@ -234,7 +255,7 @@ using namespace redsea;
 extern "C" {
 
 size_t redsea_trsm_mixed_workspace_bytes(int side, int64_t m, int64_t n, int inner) {
-    return mixed_workspace_bytes(side, m, n, inner == 0 ? 1 : inner);
+    return mixed_workspace_bytes(side, m, n, (inner & 3) == 0 ? inner | 1 : inner);
 }
 
 int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
@@ -250,7 +271,7 @@ int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_
     const int64_t ka = side == REDSEA_LEFT ? m : n;
     if (lda < std::max<int64_t>(1, ka)) return -9;
     if (ldb < std::max<int64_t>(1, m)) return -11;
-    if (inner < 0 || inner > 2) return -12;
+    if ((inner & ~(3 | REDSEA_RESIDUAL_INT8)) || (inner & 3) == 3) return -12;
     if (stats) {
         stats->iterations = 0;
         stats->eta = 0.0;
@@ -263,9 +284,9 @@ int redsea_trsm_mixed(int side, int uplo, int trans, int diag, int64_t m, int64_
     if (alpha == 0.0)
         return launch_scale(REDSEA_F64, B, m, n, ldb, 0.0, s) == hipSuccess ? REDSEA_OK
                                                                           : REDSEA_ERR_HIP;
-    if (inner == 0) inner = 1;
+    if ((inner & 3) == 0) inner |= 1;
     if (!(tol > 0.0)) tol = 1e-12;
-    if (max_iter <= 0) max_iter = inner == 1 ? 5 : 10;
+    if (max_iter <= 0) max_iter = (inner & 3) == 1 ? 5 : 10;
     return mixed_solve(side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb, inner, tol, max_iter,
                        work, work_bytes, stats, nullptr, s);
 }

@@ -10,6 +10,10 @@ namespace redsea {
 
 hipError_t launch_convert_tri(int to_bf16, const double* a, int64_t lda, int64_t k, int uplo,
                               bool unit, void* dst, hipStream_t s);
+// dst (row-major, ld ldd) := BF16 of M = op(A) restricted to A's stored
+// triangle (zero elsewhere, padding columns included; unit diagonal one).
+hipError_t launch_convert_rows_bf16(const double* a, int64_t lda, int64_t k, int uplo, bool unit,
+                                   bool op_trans, void* dst, int64_t ldd, hipStream_t s);
 hipError_t launch_scale_to_f32(const double* src, int64_t ld, int64_t m, int64_t n,
                                const double* inv, bool rhs_rows, double alpha, float* dst,
                                int64_t ldd, hipStream_t s);

@@ -152,7 +152,9 @@ def row_mixed(targets=(1e2, 1e4, 1e6), reps=3):
         rec = {"row": "mixed", "n": n, "nrhs": nrhs, "kappa_target": e["target"], "kappa1": e["kappa1"]}
         for name, fn in (("fp64", lambda: rs.trsm(dL, dB, variant="recursive", nb=256)),
                          ("fp32_ir", lambda: rs.trsm_mixed(dL, dB, inner=1)),
-                         ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2))):
+                         ("bf16_ir", lambda: rs.trsm_mixed(dL, dB, inner=2)),
+                         ("fp32_ir_int8res", lambda: rs.trsm_mixed(dL, dB, inner=1 | rs.RESIDUAL_INT8)),
+                         ("bf16_ir_int8res", lambda: rs.trsm_mixed(dL, dB, inner=2 | rs.RESIDUAL_INT8))):
             ms = _time(fn, lambda: dB.copy_(dB0), reps)
             dB.copy_(dB0)
             st = fn()

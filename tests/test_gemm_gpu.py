@@ -187,8 +187,12 @@ def test_bf16_product_elementwise(transa, transx):
     """C := C - A RN_bf16(X) with FP32 accumulation, checked element by element
     against an FP64 product of the same BF16 operands (exact products) within
     the FP32 accumulation bound (K + 1) u32 (|C| + |A||X|)."""
+    # with transa (A stored k-contiguous), transx off and K a multiple of 8 the
+    # direct-to-LDS kernel runs; the other shapes and layouts take the
+    # register-staged kernel
     for (M, N, K) in [(1, 1, 1), (37, 129, 5), (128, 128, 32), (200, 300, 150), (130, 70, 301),
-                      (515, 260, 1030)]:
+                      (515, 260, 1030), (515, 260, 1024), (130, 70, 304), (256, 300, 64),
+                      (1000, 1000, 2048), (3, 700, 8)]:
         r = synth.rng((34, M, N + K))
         A = _round_bf16(r.standard_normal((M, K)))
         X = r.standard_normal((K, N)).astype(np.float32).astype(np.float64)

@@ -38,7 +38,8 @@ def test_config2_sampled_columns(target):
     dL = rs.fortran_tensor(L)
     dB0 = rs.fortran_tensor(B)
     Bs = np.asfortranarray(B[:, COLS])
-    for inner in (1, 2):
+    # FP32 / BF16 inner solves, FP64 residual or exact INT8 emulation of it
+    for inner in (1, 2, 1 | rs.RESIDUAL_INT8, 2 | rs.RESIDUAL_INT8):
         dB = dB0.clone()
         st = rs.trsm_mixed(dL, dB, inner=inner)
         torch.cuda.synchronize()
@@ -47,4 +48,4 @@ def test_config2_sampled_columns(target):
         _say("config2 kappa %.0e inner %d: iters %d fell_back %d eta(lib) %.2e eta(oracle) %.2e"
              % (target, inner, st.iterations, st.fell_back, st.eta, eta))
         assert eta <= 1e-12, (target, inner, eta)
-        assert st.fell_back == 0 and 1 <= st.iterations <= ITER_MAX[inner], (target, inner)
+        assert st.fell_back == 0 and 1 <= st.iterations <= ITER_MAX[inner & 3], (target, inner)
