@@ -522,6 +522,11 @@ hipError_t launch_convert_rows_bf16(const double* a, int64_t lda, int64_t k, int
 
 hipError_t launch_gemm_bf16(bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+    // 256 x 128 tiles on eight waves; short products (the updates near the
+    // leaves, where 256-row tiles would leave most CUs idle) on 64 x 64 tiles
+    // of four waves
+    if (a_trans && !rhs_trans && g.M <= 512 && bf16_dma_ok<64, 64, 2, 2, 4>(g))
+        return bf16_dma_launch<64, 64, 2, 2, 4>(g, s);
     if (a_trans && !rhs_trans && bf16_dma_ok<256, 128, 4, 2, 2>(g))
         return bf16_dma_launch<256, 128, 4, 2, 2>(g, s);
     const int64_t tiles = ((g.M + HB_BM - 1) / HB_BM) * ((g.N + HB_BN - 1) / HB_BN);
