@@ -88,12 +88,14 @@ typedef enum {
  * triangular matrix; 1 for a unit diagonal) on the device and waits for that
  * value, so an AUTO call with kappa = 0 synchronizes the stream once.  An
  * AUTO nb beside a fixed variant or precision is 256 for order(A) > 128,
- * else 128. */
+ * else 128.  tile only concerns the batched solver (see redsea_batched_tune)
+ * and is ignored elsewhere. */
 typedef struct {
     int variant;   /* redsea_variant   */
     int nb;        /* leaf size or 0   */
     int precision; /* redsea_precision */
     double kappa;  /* condition estimate or 0 */
+    int tile;      /* batched solves: task shape 1..REDSEA_BATCH_TILES, 0 = AUTO */
 } redsea_opts;
 
 enum {
@@ -222,6 +224,33 @@ enum { REDSEA_TRMM_MFMA = 0, REDSEA_TRMM_INT8 = 1 };
 int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                 double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
                 double beta, void* C, int64_t ldc, int method, void* stream);
+
+/*
+ * Autotuner of the batched solver's task shape (spec batching pattern:
+ * tile shapes picked by the project's own tuner).  Candidates t = 1..12 are
+ * {16, 32} right-hand sides per wave task (a task of 32 uses each loaded
+ * block of the triangle for two groups of 16, halving reads of the matrix)
+ * x {1, 2, 4} steps of the left-looking product with operands in flight
+ * x {2, 4} workgroups of four waves per CU in the persistent grid, in that
+ * nesting order (t = 1: 16 columns, depth 1, 2 workgroups per CU); every
+ * candidate does the same arithmetic on every column, so the result does not
+ * depend on the pick.  Generates, on the device, left / lower
+ * / no-transpose systems of the given orders k[i] and right-hand-side counts
+ * nrhs[i] (HOST arrays; strict lower part uniform in (-1, 1), diagonal
+ * 1 + sum |row|), times every candidate (median of `reps` after a warm-up),
+ * writes the milliseconds to ms[0..11] (HOST, optional) and the fastest
+ * candidate to *best (ties: the lower index), and remembers that pick for
+ * later batches of the same kind on this device (data type, unit diagonal,
+ * and the rounded log2 of the system count, of the largest and median orders
+ * and of the median right-hand-side count).  Batched calls with opts->tile = 0
+ * use a remembered pick, else tune first when the environment variable
+ * REDSEA_TUNE is 1, else take candidate 1.  Synchronous; allocates and frees
+ * its own device memory.  Argument numbers: dtype 1, diag 2, count 3, k 4,
+ * nrhs 5, reps 6, ms 7, best 8.
+ */
+enum { REDSEA_BATCH_TILES = 12 };
+int redsea_batched_tune(int dtype, int diag, int64_t count, const int64_t* k, const int64_t* nrhs,
+                        int reps, double* ms, int* best);
 
 /* Statistics of one mixed-precision solve (host struct). */
 typedef struct {

@@ -6,8 +6,8 @@ kernels for gfx950.
 """
 from ._binding import (BatchPlan, EXPORTS, KERNEL_CLASSES, LIB_PATH, trace_begin, trace_end, MixedStats, Opts, RedseaError, fortran_tensor, gemm_update, lib,
                        mfma_peak, mixed_workspace_bytes, schedule, status_string, trsm, trsm_batched,
-                       trsm_mixed, trsm_noalloc, trmm, RESIDUAL_INT8, version)
+                       trsm_mixed, trsm_noalloc, trmm, RESIDUAL_INT8, batched_tune, version)
 
 __all__ = ["BatchPlan", "EXPORTS", "KERNEL_CLASSES", "LIB_PATH", "trace_begin", "trace_end", "MixedStats", "Opts", "RedseaError", "fortran_tensor", "gemm_update", "lib",
            "mfma_peak", "mixed_workspace_bytes", "schedule", "status_string", "trsm", "trsm_batched",
-           "trsm_mixed", "trsm_noalloc", "trmm", "RESIDUAL_INT8", "version"]
+           "trsm_mixed", "trsm_noalloc", "trmm", "RESIDUAL_INT8", "batched_tune", "version"]

@@ -19,6 +19,7 @@ EXPORTS = (
     "redsea_trsm",
     "redsea_trsm_noalloc",
     "redsea_trsm_batched",
+    "redsea_batched_tune",
     "redsea_trsm_mixed",
     "redsea_trmm",
     "redsea_trsm_mixed_workspace_bytes",
@@ -61,7 +62,7 @@ class RedseaError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int), ("nb", ctypes.c_int), ("precision", ctypes.c_int),
-                ("kappa", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("tile", ctypes.c_int)]
 
 
 class MixedStats(ctypes.Structure):
@@ -107,6 +108,9 @@ def lib() -> ctypes.CDLL:
     L.redsea_gemm_update.restype = cint
     L.redsea_gemm_update.argtypes = [cint, cint, cint, i64, i64, i64, ptr, i64, ptr, i64, ptr, i64,
                                      cint, ptr]
+    L.redsea_batched_tune.restype = cint
+    L.redsea_batched_tune.argtypes = [cint, cint, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), cint,
+                                      ctypes.POINTER(dbl), ctypes.POINTER(cint)]
     L.redsea_batched_plan_create.restype = cint
     L.redsea_batched_plan_create.argtypes = [cint, cint, cint, cint, cint, i64, ctypes.POINTER(i64),
                                              ctypes.POINTER(i64), dbl, ctypes.POINTER(ptr),
@@ -215,8 +219,22 @@ def trsm_noalloc(A, B, side="L", uplo="L", trans="N", diag="N", alpha: float = 1
     return B
 
 
+def batched_tune(orders, nrhs, dtype: str = "f64", diag="N", reps: int = 2):
+    """Time every batched task shape on generated systems of these shapes;
+    returns (best candidate 1..12, milliseconds per candidate)."""
+    count = len(orders)
+    i64 = ctypes.c_int64
+    ks = (i64 * max(1, count))(*[int(x) for x in orders])
+    rs = (i64 * max(1, count))(*[int(x) for x in nrhs])
+    ms = (ctypes.c_double * 12)()
+    best = ctypes.c_int()
+    _check(lib().redsea_batched_tune(0 if dtype == "f64" else 1, DIAG[diag], count, ks, rs,
+                                     int(reps), ms, ctypes.byref(best)))
+    return best.value, [float(x) for x in ms]
+
+
 def trsm_batched(As: Sequence, Bs: Sequence, info, side="L", uplo="L", trans="N", diag="N",
-                 alpha: float = 1.0, variant="auto", nb: int = 0, stream=None):
+                 alpha: float = 1.0, variant="auto", nb: int = 0, tile: int = 0, stream=None):
     """Batch of independent in-place solves; info is an int32 device tensor."""
     count = len(Bs)
     i64 = ctypes.c_int64
@@ -226,7 +244,7 @@ def trsm_batched(As: Sequence, Bs: Sequence, info, side="L", uplo="L", trans="N"
     ldbs = (i64 * count)(*[_ld(b) for b in Bs])
     aps = (ctypes.c_void_p * count)(*[a.data_ptr() for a in As])
     bps = (ctypes.c_void_p * count)(*[b.data_ptr() for b in Bs])
-    opts = Opts(VARIANT[variant], int(nb), 0)
+    opts = Opts(VARIANT[variant], int(nb), 0, 0.0, int(tile))
     dt = _dtype_code(Bs[0]) if count else 0
     rc = lib().redsea_trsm_batched(dt, SIDE[side], UPLO[uplo], TRANS[trans], DIAG[diag], count,
                                    ms, ns, float(alpha), aps, ldas, bps, ldbs, info.data_ptr(),
@@ -249,11 +267,11 @@ class BatchPlan:
     so it can be captured in a graph.  The tensors must stay alive."""
 
     def __init__(self, As, Bs, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
-                 variant="auto", nb: int = 0):
+                 variant="auto", nb: int = 0, tile: int = 0):
         self._keep = (list(As), list(Bs))
         count, ms, ns, aps, ldas, bps, ldbs = _batch_arrays(As, Bs)
         self.count = count
-        opts = Opts(VARIANT[variant], int(nb), 0)
+        opts = Opts(VARIANT[variant], int(nb), 0, 0.0, int(tile))
         h = ctypes.c_void_p()
         dt = _dtype_code(Bs[0]) if count else 0
         _check(lib().redsea_batched_plan_create(dt, SIDE[side], UPLO[uplo], TRANS[trans],

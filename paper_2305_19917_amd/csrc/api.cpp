@@ -558,7 +558,7 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
     if (precision < 0 || precision > 3) return -13;
     if (m == 0 || n == 0) return REDSEA_OK;
     hipStream_t s = (hipStream_t)stream;
-    redsea_opts chosen = opts ? *opts : redsea_opts{0, 0, 0, 0.0};
+    redsea_opts chosen = opts ? *opts : redsea_opts{0, 0, 0, 0.0, 0};
     if (variant == 0 && nb == 0 && precision == 0 && alpha != 0.0) {
         // learned picker (falls back to the exhaustive tuner when asked to and
         // not confident); a condition estimate, when not given, is taken as

@@ -25,8 +25,21 @@ struct BatchTask {
 constexpr int64_t kBatchMaxOrder = 1024;  // panel of 16 columns in LDS
 
 hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_t s);
-hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
-                          int ntasks, int* counter, int* info, int64_t kmax, double alpha,
-                          int grid, hipStream_t s);
+// groups: column groups of 16 per task (1 or 2; with 2 a wave solves 32
+// right-hand sides and each block of the triangle it loads feeds both).
+// depth: steps of the left-looking product whose operands are in flight (1,
+// 2 or 4).  Neither changes the arithmetic: results are bitwise the same.
+hipError_t launch_batched(int dtype, bool unit, int groups, int depth, const BatchSys* sys,
+                          const BatchTask* tasks, int ntasks, int* counter, int* info,
+                          double alpha, int grid, hipStream_t s);
+
+// Task shapes the batched solver can run (index = tile option - 1):
+// {column groups per task, operand prefetch depth, workgroups of four waves
+// per CU}.
+constexpr int kBatchTiles = 12;
+constexpr int kBatchTileGroups[kBatchTiles] = {1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+constexpr int kBatchTileDepth[kBatchTiles] = {1, 1, 2, 2, 4, 4, 1, 1, 2, 2, 4, 4};
+constexpr int kBatchTileWgPerCu[kBatchTiles] = {2, 4, 2, 4, 2, 4, 2, 4, 2, 4, 2, 4};
+constexpr int kBatchTileDefault = 1;
 
 }  // namespace redsea

@@ -40,15 +40,18 @@ __global__ void batch_reset_kernel(int* counter, int* info, int64_t count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-template <typename TS, bool UNIT>
+template <typename TS, bool UNIT, int W, int D>
 __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict__ sys,
                                                       const BatchTask* __restrict__ tasks,
                                                       int ntasks, int* __restrict__ counter,
                                                       int* __restrict__ info, double alpha) {
-    __shared__ double Xs[4][16][17];  // per-wave gather buffer
-    __shared__ double Ls[4][16 * 16]; // per-wave diagonal block, (j, i) at [i*16 + j]
-    __shared__ double Rs[4][16];      // per-wave 1 / diagonal
+    __shared__ double Xs[4][W][16][17];  // per-wave gather buffer, one per column group
+    __shared__ double Ls[4][16 * 16];    // per-wave diagonal block, (j, i) at [i*16 + j]
+    __shared__ double Rs[4][16];         // per-wave 1 / diagonal
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    // the group whose column c this lane solves in the substitution (the four
+    // row slices g of a column split evenly over the W groups)
+    const int sg = W == 1 ? 0 : (g >> 1);
     for (;;) {
         int t = 0;
         if (lane == 0) t = atomicAdd(counter, 1);
@@ -59,20 +62,24 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
         const TS* A = (const TS*)S.a;
         TS* B = (TS*)S.b;
         const int64_t k = S.k, c0 = task.c0;
-        const int wcols = (int)(S.nrhs - c0 < 16 ? S.nrhs - c0 : 16);
-        const bool colok = c < wcols;
+        bool colok[W];
+        int64_t bcol[W];
+#pragma unroll
+        for (int G = 0; G < W; ++G) {
+            colok[G] = c0 + 16 * G + c < S.nrhs;
+            bcol[G] = S.b_off + (c0 + 16 * G + (colok[G] ? c : 0)) * S.bc;
+        }
         const int nblk = (int)((k + 15) / 16);
-        const int64_t bcol = S.b_off + (c0 + (colok ? c : 0)) * S.bc;
         // Operand reads.  FP64: predicated loads.  FP32: branch-free, an
         // out-of-range lane reads a valid element (the first of the system or
         // of the task's first column) and discards it; with a predicated load
         // the widening to FP64 sits inside the branch and makes every load
         // wait for its data before the next is issued.
         const int64_t bsafe = S.b_off + c0 * S.bc;
-        auto bget = [&](int64_t row) -> double {
-            const bool ok = colok && row < k;
-            if constexpr (sizeof(TS) == 8) return ok ? (double)B[bcol + row * S.br] : 0.0;
-            const TS v = B[ok ? bcol + row * S.br : bsafe];
+        auto bget = [&](int G, int64_t row) -> double {
+            const bool ok = colok[G] && row < k;
+            if constexpr (sizeof(TS) == 8) return ok ? (double)B[bcol[G] + row * S.br] : 0.0;
+            const TS v = B[ok ? bcol[G] + row * S.br : bsafe];
             return ok ? (double)v : 0.0;
         };
         auto aget = [&](int64_t row, int64_t col) -> double {
@@ -83,10 +90,12 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
         };
         int bad = 0;
         for (int p = 0; p < nblk; ++p) {
-            v4d acc;
+            v4d acc[W];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[r] = alpha != 0.0 ? alpha * bget(16 * p + g + 4 * r) : 0.0;  // BLAS: B := 0
+            for (int G = 0; G < W; ++G)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[G][r] = alpha != 0.0 ? alpha * bget(G, 16 * p + g + 4 * r) : 0.0;  // BLAS: B := 0
             if (alpha != 0.0) {
                 // diagonal block (identity past the order) and the reciprocals
                 // of its diagonal; independent of the products below
@@ -101,50 +110,62 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                     Ls[w][c * 16 + i] = v;
                     if (!UNIT && i == c) Rs[w][c] = 1.0 / v;
                 }
-                // acc -= L_pq X_q, q < p; operands of q+1 requested before q's MFMAs
-                double xa[4], aa[4];
-                if (p > 0) {
+                // acc -= L_pq X_q, q < p, on the matrix cores; the operands
+                // of step q + D are requested right after step q's MFMAs have
+                // used their registers (a ring of D operand sets), so D - 1
+                // steps of loads are in flight while one multiplies; each
+                // block of L feeds the W column groups
+                double xa[D][W][4], aa[D][4];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        xa[kk] = bget(4 * kk + g);
-                        aa[kk] = -aget(16 * p + c, 4 * kk + g);
-                    }
-                }
-                for (int q = 0; q < p; ++q) {
-                    double xn[4], an[4];
-                    if (q + 1 < p) {
+                for (int d = 0; d < D; ++d)
+                    if (d < p) {
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) {
-                            xn[kk] = bget(16 * (q + 1) + 4 * kk + g);
-                            an[kk] = -aget(16 * p + c, 16 * (q + 1) + 4 * kk + g);
+#pragma unroll
+                            for (int G = 0; G < W; ++G) xa[d][G][kk] = bget(G, 16 * d + 4 * kk + g);
+                            aa[d][kk] = -aget(16 * p + c, 16 * d + 4 * kk + g);
                         }
                     }
+                for (int q0 = 0; q0 < p; q0 += D) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[kk], xa[kk], acc, 0, 0, 0);
-                    if (q + 1 < p) {
+                    for (int d = 0; d < D; ++d) {
+                        const int q = q0 + d;
+                        if (q >= p) break;  // uniform over the wave
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            xa[kk] = xn[kk];
-                            aa[kk] = an[kk];
+                        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                            for (int G = 0; G < W; ++G)
+                                acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[d][kk], xa[d][G][kk],
+                                                                             acc[G], 0, 0, 0);
+                        if (q + D < p) {
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+                                for (int G = 0; G < W; ++G)
+                                    xa[d][G][kk] = bget(G, 16 * (q + D) + 4 * kk + g);
+                                aa[d][kk] = -aget(16 * p + c, 16 * (q + D) + 4 * kk + g);
+                            }
                         }
                     }
                 }
-                // the column's rows of the block
+                // the columns' rows of the block
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Xs[w][g + 4 * r][c] = acc[r];
+                for (int G = 0; G < W; ++G)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Xs[w][G][g + 4 * r][c] = acc[G][r];
                 wave_sync();
                 // substitution (axpy order), pipelined by one row as in the
-                // leaf solver; the fast divisions are redone in IEEE
-                // arithmetic for the whole block if any operand of the wave
-                // left their guard (same result wherever it held)
+                // leaf solver, column c of group sg in this lane; the fast
+                // divisions are redone in IEEE arithmetic for the whole block
+                // if any operand of the wave left their guard (same result
+                // wherever it held)
                 double y[16];
                 auto subst = [&](auto fast) {
                     double dg[16], rd[16], cur[16], nxt[16];
                     bool dok[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        y[i] = Xs[w][i][c];
+                        y[i] = Xs[w][sg][i][c];
                         if (!UNIT) {
                             dg[i] = Ls[w][i * 16 + i];
                             rd[i] = Rs[w][i];
@@ -184,23 +205,39 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                     return ok;
                 };
                 if (!__all(subst(std::true_type()))) subst(std::false_type());
+                if (W == 1) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];
-                    const double v23 = g == 2 ? y[4 * r + 2] : y[4 * r + 3];
-                    acc[r] = g < 2 ? v01 : v23;
+                    for (int r = 0; r < 4; ++r) {
+                        const double v01 = g == 0 ? y[4 * r] : y[4 * r + 1];
+                        const double v23 = g == 2 ? y[4 * r + 2] : y[4 * r + 3];
+                        acc[0][r] = g < 2 ? v01 : v23;
+                    }
+                } else {
+                    // each group's solved column goes back through LDS to the
+                    // accumulator layout of both groups
+                    wave_sync();
+                    if ((g & 1) == 0)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) Xs[w][sg][i][c] = y[i];
+                    wave_sync();
+#pragma unroll
+                    for (int G = 0; G < W; ++G)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[G][r] = Xs[w][G][g + 4 * r][c];
                 }
                 wave_sync();  // Xs and Ls are reused by the next block
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = 16 * p + g + 4 * r;
-                if (colok && row < k) {
-                    const TS v = (TS)acc[r];
-                    B[bcol + row * S.br] = v;
-                    if (!__builtin_isfinite((double)v)) bad = 1;
+            for (int G = 0; G < W; ++G)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = 16 * p + g + 4 * r;
+                    if (colok[G] && row < k) {
+                        const TS v = (TS)acc[G][r];
+                        B[bcol[G] + row * S.br] = v;
+                        if (!__builtin_isfinite((double)v)) bad = 1;
+                    }
                 }
-            }
         }
         // the stores of this task are visible to its own later loads (same
         // wave, program order); flag a non-finite result of the system
@@ -219,26 +256,42 @@ hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_batched(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
-                          int ntasks, int* counter, int* info, int64_t kmax, double alpha,
-                          int grid, hipStream_t s) {
-    (void)kmax;
+template <int W, int D>
+void launch_batched_wd(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
+                       int ntasks, int* counter, int* info, double alpha, int grid, hipStream_t s) {
     if (dtype == 0) {
         if (unit)
-            hipLaunchKernelGGL((batched_kernel<double, true>), dim3(grid), dim3(256), 0, s, sys,
-                               tasks, ntasks, counter, info, alpha);
+            hipLaunchKernelGGL((batched_kernel<double, true, W, D>), dim3(grid), dim3(256), 0, s,
+                               sys, tasks, ntasks, counter, info, alpha);
         else
-            hipLaunchKernelGGL((batched_kernel<double, false>), dim3(grid), dim3(256), 0, s, sys,
-                               tasks, ntasks, counter, info, alpha);
+            hipLaunchKernelGGL((batched_kernel<double, false, W, D>), dim3(grid), dim3(256), 0, s,
+                               sys, tasks, ntasks, counter, info, alpha);
     } else {
         if (unit)
-            hipLaunchKernelGGL((batched_kernel<float, true>), dim3(grid), dim3(256), 0, s, sys,
-                               tasks, ntasks, counter, info, alpha);
+            hipLaunchKernelGGL((batched_kernel<float, true, W, D>), dim3(grid), dim3(256), 0, s,
+                               sys, tasks, ntasks, counter, info, alpha);
         else
-            hipLaunchKernelGGL((batched_kernel<float, false>), dim3(grid), dim3(256), 0, s, sys,
-                               tasks, ntasks, counter, info, alpha);
+            hipLaunchKernelGGL((batched_kernel<float, false, W, D>), dim3(grid), dim3(256), 0, s,
+                               sys, tasks, ntasks, counter, info, alpha);
     }
-    return hipGetLastError();
+}
+
+hipError_t launch_batched(int dtype, bool unit, int groups, int depth, const BatchSys* sys,
+                          const BatchTask* tasks, int ntasks, int* counter, int* info,
+                          double alpha, int grid, hipStream_t s) {
+#define REDSEA_BATCHED_CASE(W, D)                                                            \
+    if (groups == W && depth == D) {                                                         \
+        launch_batched_wd<W, D>(dtype, unit, sys, tasks, ntasks, counter, info, alpha, grid, s); \
+        return hipGetLastError();                                                            \
+    }
+    REDSEA_BATCHED_CASE(1, 1)
+    REDSEA_BATCHED_CASE(1, 2)
+    REDSEA_BATCHED_CASE(1, 4)
+    REDSEA_BATCHED_CASE(2, 1)
+    REDSEA_BATCHED_CASE(2, 2)
+    REDSEA_BATCHED_CASE(2, 4)
+#undef REDSEA_BATCHED_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace redsea

@@ -286,6 +286,7 @@ int redsea_tune_shape(int dtype, int64_t n, int64_t nrhs, double c, uint64_t see
         o.nb = nb;
         o.precision = p;
         o.kappa = 0.0;
+        o.tile = 0;
         std::vector<float> t;
         for (int r = 0; r <= reps && rc == REDSEA_OK; ++r) {
             if (hipMemcpyAsync(B, B0, bn * es, hipMemcpyDeviceToDevice, s) != hipSuccess) {

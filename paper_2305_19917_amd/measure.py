@@ -15,7 +15,8 @@ Rows:
            iterations and the library's own final backward error)
   mixed1e4 the same at kappa_1 ~ 1e4 only, one timed repetition (for tracing)
   batched  2000 systems, n log-uniform in [32, 1024], nrhs in [1, 256], FP64
-           and FP32, one plan launch (eager and hipGraph replay)
+           and FP32: every task shape, the autotuner's pick, and one plan
+           launch with that pick (eager and hipGraph replay)
 
 Timing: hipEvents on the stream, B restored by a device copy outside the
 events, median of the repetitions.  Inputs are the seeded synthetic systems of
@@ -180,7 +181,15 @@ def row_batched():
         Bs = [rs.fortran_tensor(synth.rhs_normal(int(n), int(k), (3, i, 1)).astype(dt))
               for i, (n, k) in enumerate(zip(ns, ks))]
         info = torch.zeros(len(Bs), dtype=torch.int32, device="cuda")
-        plan = rs.BatchPlan(As, Bs)
+        # every task shape on this batch, and the autotuner's pick (which it
+        # makes on generated systems of the same shapes)
+        per_tile = {}
+        for tile in range(1, 13):
+            p_t = rs.BatchPlan(As, Bs, tile=tile)
+            per_tile[tile] = round(_time(lambda: p_t.run(info), lambda: None, 10), 4)
+            p_t.close()
+        best, tune_ms = rs.batched_tune(ns, ks, dtype="f64" if es == 8 else "f32", reps=3)
+        plan = rs.BatchPlan(As, Bs, tile=best)
         ms = _time(lambda: plan.run(info), lambda: None, 20)
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
@@ -189,7 +198,9 @@ def row_batched():
             plan.run(info, stream=s)
         torch.cuda.synchronize()
         gms = _time(lambda: g.replay(), lambda: None, 20)
-        _emit({"row": "batched", "dtype": np.dtype(dt).name, "systems": len(Bs), "ms": round(ms, 4),
+        _emit({"row": "batched", "dtype": np.dtype(dt).name, "systems": len(Bs), "tile": best,
+               "ms_per_tile": per_tile, "tuner_ms_per_tile": [round(x, 4) for x in tune_ms],
+               "ms": round(ms, 4),
                "graph_ms": round(gms, 4), "systems_per_s": round(len(Bs) / (gms * 1e-3)),
                "tflops": round(flops / (gms * 1e-3) / 1e12, 3),
                "algorithmic_gbs": round(byts / (gms * 1e-3) / 1e9, 1),

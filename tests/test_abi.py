@@ -124,7 +124,7 @@ static fp every_entry[] = {
     %s
 };
 int main(void) {
-    redsea_opts o = {REDSEA_VARIANT_RECURSIVE, 256, REDSEA_PREC_NATIVE, 0.0};
+    redsea_opts o = {REDSEA_VARIANT_RECURSIVE, 256, REDSEA_PREC_NATIVE, 0.0, 0};
     redsea_mixed_stats st;
     memset(&st, 0, sizeof st);
     (void)o;
@@ -151,3 +151,19 @@ def test_header_compiles_standalone_and_links(tmp_path, compiler, std, ext):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     assert out[0] == rs.version() and out[1] == "success"
     assert int(out[2]) == len(_declared())
+
+
+def test_batched_tune_argument_errors():
+    L = rs.lib()
+    i64 = ctypes.c_int64
+    k = (i64 * 1)(10)
+    r = (i64 * 1)(3)
+    best = ctypes.c_int(0)
+    assert L.redsea_batched_tune(5, 0, 1, k, r, 1, None, ctypes.byref(best)) == -1
+    assert L.redsea_batched_tune(0, 3, 1, k, r, 1, None, ctypes.byref(best)) == -2
+    assert L.redsea_batched_tune(0, 0, -1, k, r, 1, None, ctypes.byref(best)) == -3
+    assert L.redsea_batched_tune(0, 0, 1, None, r, 1, None, ctypes.byref(best)) == -4
+    assert L.redsea_batched_tune(0, 0, 1, k, r, 0, None, ctypes.byref(best)) == -6
+    assert L.redsea_batched_tune(0, 0, 1, k, r, 1, None, None) == -8
+    assert L.redsea_batched_tune(0, 0, 0, None, None, 1, None, ctypes.byref(best)) == 0
+    assert best.value == 1

@@ -214,3 +214,45 @@ def test_alpha_zero_overwrites_nonfinite_with_zero():
     assert np.all(info == 0)
     for X in Xs:
         assert np.array_equal(X, np.zeros_like(X))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_every_task_shape_gives_the_same_bits(dtype):
+    """The twelve task shapes the tuner chooses from (16 or 32 right-hand
+    sides per wave task, operand prefetch depth 1, 2 or 4, 2 or 4 workgroups
+    per CU) do the same arithmetic on
+    every column, so their results agree bitwise; checked on a batch of
+    uneven systems with ragged column counts, also against the oracle."""
+    As, Bs = _make(150, (3, 6, 2), n_range=(16, 700), nrhs_range=(1, 100))
+    outs = []
+    for tile in range(1, 13):
+        Xs, info = _run(As, Bs, dtype, tile=tile)
+        assert np.all(info == 0), tile
+        outs.append(Xs)
+    for tile in range(2, 13):
+        for i, (a, b) in enumerate(zip(outs[0], outs[tile - 1])):
+            assert np.array_equal(a, b), (tile, i)
+    bound = 1e-14 if dtype == np.float64 else 5e-6
+    for A, B, X in zip(As[:20], Bs[:20], outs[3][:20]):
+        A32, B32 = A.astype(dtype).astype(np.float64), B.astype(dtype).astype(np.float64)
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, A32, B32, X) <= bound * A.shape[0]
+
+
+@pytest.mark.parametrize("side,uplo,trans,diag", [(0, 1, 1, 0), (1, 0, 0, 1), (1, 1, 1, 0)])
+def test_wide_tasks_all_flags(side, uplo, trans, diag):
+    As, Bs = _make(40, (3, 7, side), n_range=(20, 300), nrhs_range=(1, 70), side=side, uplo=uplo,
+                   trans=trans, diag=diag)
+    X16, i16 = _run(As, Bs, side=side, uplo=uplo, trans=trans, diag=diag, alpha=-0.5, tile=1)
+    X32, i32 = _run(As, Bs, side=side, uplo=uplo, trans=trans, diag=diag, alpha=-0.5, tile=12)
+    assert np.all(i16 == 0) and np.all(i32 == 0)
+    for A, B, a, b in zip(As, Bs, X16, X32):
+        assert np.array_equal(a, b)
+        assert oracle.backward_error(side, uplo, trans, diag, -0.5, A, B, b) <= 1e-14 * A.shape[0]
+
+
+def test_tuner_picks_its_fastest_candidate():
+    ns, ks = synth.batch_shapes(300, (3, 8, 2))
+    best, ms = rs.batched_tune(ns, ks, reps=2)
+    _say("batched tuner: best", best, "ms", ["%.3f" % x for x in ms])
+    assert 1 <= best <= 12 and all(x > 0 for x in ms)
+    assert ms[best - 1] == min(ms) and ms.index(min(ms)) == best - 1
