@@ -365,9 +365,11 @@ int redsea_candidate(int index, int* variant, int* nb, int* precision);
  * device (strict lower part uniform in (-1, 1) from a counter-based hash of
  * (seed, i, j); diagonal 1 + sum|row| when c <= 0, else the constant
  * c * (1 + max row sum), which sets the condition number), then times each
- * listed candidate: `reps` runs after one warm-up, B restored between runs,
- * median in milliseconds written to ms[i] (-1 for a candidate that does not
- * apply, e.g. refinement for FP32 data).  cand: HOST array of ncand indices.
+ * listed candidate in the given order: `reps` runs after one warm-up, B
+ * restored between runs, median in milliseconds written to ms[i] (-1 for a
+ * candidate that does not apply, e.g. refinement for FP32 data); a candidate
+ * whose warm-up run already takes more than three times the best median so
+ * far is not repeated and reports that one run.  cand: HOST array of ncand indices.
  * Synchronous; allocates and frees its own device buffers.  Argument
  * numbers: dtype 1, n 2, nrhs 3, c 4, seed 5, reps 6, cand 7, ncand 8, ms 9,
  * stream 10.
@@ -426,7 +428,8 @@ int redsea_mlp_load(const char* path);
  * TFLOP/s. */
 int64_t redsea_mfma_peak(int dtype, int64_t iters, void* out, int64_t out_elems, void* stream);
 
-/* Library version as "major.minor.patch". */
+/* Library version as "major.minor.patch+build", build being the first 12 hex
+ * digits of the SHA-256 of the sources it was compiled from. */
 const char* redsea_version(void);
 
 #ifdef __cplusplus

@@ -1,6 +1,6 @@
 """FP64 CPU reference of the picker network (TEST INFRASTRUCTURE).
 
-The network is y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (5 -> 64 -> 64 ->
+The network is y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 (4 -> 64 -> 64 ->
 45) with the masked mean-squared-error loss
 L = sum(mask (Y - T)^2) / sum(mask).  The gradient below is the textbook
 backward pass (chain rule through each affine map and ReLU), written out in
@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
-SIZES = (5, 64, 64, 45)
+SIZES = (4, 64, 64, 45)
 
 
 def count() -> int:

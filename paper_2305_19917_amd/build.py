@@ -4,6 +4,7 @@ Every source under csrc/ is compiled by hipcc for gfx950 only; the objects
 are linked into paper_2305_19917_amd/libredsea.so, next to this file.
 """
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -30,9 +31,20 @@ def sources():
     return out
 
 
-def _compile(src):
+def build_id() -> str:
+    """First 12 hex digits of the SHA-256 of every source and the header:
+    the library reports it in its version string, so timing records can be
+    tied to the code that produced them."""
+    h = hashlib.sha256()
+    for p in sources() + [os.path.join(os.path.dirname(HERE), "include", "redsea.h")]:
+        h.update(os.path.basename(p).encode())
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:12]
+
+
+def _compile(src, bid):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + ['-DREDSEA_BUILD_ID="%s"' % bid, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -45,8 +57,9 @@ def build(jobs: int = 0) -> str:
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
+    bid = build_id()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda s: _compile(s, bid), srcs))
     for _, err in results:
         if err.strip():
             sys.stderr.write(err + "\n")

@@ -1,6 +1,6 @@
 // Kernels of the learned schedule picker and of the tuner's data generator.
 //
-// The picker is a 3-layer FP32 MLP (5 -> 64 -> 64 -> 45, ReLU) regressing the
+// The picker is a 3-layer FP32 MLP (4 -> 64 -> 64 -> 45, ReLU) regressing the
 // log time of each candidate schedule.  Training and inference run on these
 // hand-written kernels: one thread per output element, every reduction over
 // the batch done by one thread in a fixed order, so results are

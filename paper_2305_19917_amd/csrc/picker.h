@@ -6,9 +6,10 @@
 
 namespace redsea {
 
-// 5 -> 64 -> 64 -> 45, parameters packed W1, b1, W2, b2, W3, b3 (row-major).
+// 4 -> 64 -> 64 -> 45, parameters packed W1, b1, W2, b2, W3, b3 (row-major).
+// Inputs: log2 n, log2 nrhs, dtype, log10 kappa (normalised).
 struct MlpShape {
-    static constexpr int in = 5, h1 = 64, h2 = 64, out = 45;
+    static constexpr int in = 4, h1 = 64, h2 = 64, out = 45;
     constexpr int w1() const { return 0; }
     constexpr int b1() const { return h1 * in; }
     constexpr int w2() const { return b1() + h1; }

@@ -27,7 +27,7 @@ const int kNbs[5] = {32, 64, 128, 256, 512};
 
 struct Net {
     bool loaded = false;
-    float mu[5], sd[5];
+    float mu[MlpShape::in], sd[MlpShape::in];
     float lo[2], hi[2];  // training range of log2 n and log2 nrhs
     std::vector<float> P;
 };
@@ -43,11 +43,11 @@ bool load_file(const char* path, Net& net) {
     int ver = 0, in = 0, h1 = 0, h2 = 0, out = 0;
     f >> magic >> ver >> in >> h1 >> h2 >> out;
     const MlpShape S;
-    if (!f || magic != "redsea-mlp" || ver != 1 || in != S.in || h1 != S.h1 || h2 != S.h2 ||
+    if (!f || magic != "redsea-mlp" || ver != 2 || in != S.in || h1 != S.h1 || h2 != S.h2 ||
         out != S.out)
         return false;
-    for (int i = 0; i < 5; ++i) f >> net.mu[i];
-    for (int i = 0; i < 5; ++i) f >> net.sd[i];
+    for (int i = 0; i < S.in; ++i) f >> net.mu[i];
+    for (int i = 0; i < S.in; ++i) f >> net.sd[i];
     f >> net.lo[0] >> net.hi[0] >> net.lo[1] >> net.hi[1];
     net.P.resize(S.count());
     for (int i = 0; i < S.count(); ++i) f >> net.P[i];
@@ -71,7 +71,7 @@ void ensure_loaded() {
 }
 
 // y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 on the host (double accumulation)
-void host_forward(const Net& net, const float x[5], double y[45]) {
+void host_forward(const Net& net, const float x[MlpShape::in], double y[45]) {
     const MlpShape S;
     const float* P = net.P.data();
     double h1[64], h2[64];
@@ -118,9 +118,9 @@ int pick_candidate(int dtype, int64_t n, int64_t nrhs, double kappa, int* confid
         return 3 * idx;
     }
     const double lk = std::log10(kappa > 1.0 ? kappa : 1.0);
-    const double raw[5] = {ln, lr, (double)dtype, lk, 0.0};
-    float x[5];
-    for (int i = 0; i < 5; ++i) x[i] = (float)((raw[i] - g_net.mu[i]) / g_net.sd[i]);
+    const double raw[MlpShape::in] = {ln, lr, (double)dtype, lk};
+    float x[MlpShape::in];
+    for (int i = 0; i < MlpShape::in; ++i) x[i] = (float)((raw[i] - g_net.mu[i]) / g_net.sd[i]);
     double y[45];
     host_forward(g_net, x, y);
     int best = -1, second = -1;
@@ -274,6 +274,7 @@ int redsea_tune_shape(int dtype, int64_t n, int64_t nrhs, double c, uint64_t see
         return REDSEA_ERR_HIP;
     }
     int rc = REDSEA_OK;
+    double best = -1.0;  // best median so far
     for (int ci = 0; ci < ncand && rc == REDSEA_OK; ++ci) {
         int v, nb, p;
         decode_candidate(cand[ci], &v, &nb, &p);
@@ -301,10 +302,17 @@ int redsea_tune_shape(int dtype, int64_t n, int64_t nrhs, double c, uint64_t see
             float el = 0.f;
             (void)hipEventElapsedTime(&el, e0, e1);
             if (r > 0) t.push_back(el);  // the first run warms up
+            // a candidate far behind the best is not repeated: its one run
+            // (an upper bound of its time, warm-up included) is reported
+            if (r == 0 && best > 0.0 && el > 3.0 * best) {
+                t.push_back(el);
+                break;
+            }
         }
         if (rc == REDSEA_OK) {
             std::sort(t.begin(), t.end());
             ms[ci] = t[t.size() / 2];
+            if (best < 0.0 || ms[ci] < best) best = ms[ci];
         }
     }
     (void)hipEventDestroy(e0);

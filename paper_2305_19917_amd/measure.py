@@ -9,6 +9,9 @@ Rows:
   thin     FP64 n = 8192, nrhs = 1024: upper/transposed and lower/unit-diagonal
            (diagonal stored as NaN), plus lower/N for nrhs in {1, 8, 32}, with
            the HBM rate implied by the algorithmic bytes
+  sides    FP64 n = nrhs = 8192: all side / uplo / trans combinations, and the
+           triangular product (redsea_trmm) on the matrix cores and by INT8
+           emulation
   mixed    FP64 in/out, n = 16384, nrhs = 4096, conditioning family with
            kappa_1 in {1e2, 1e4, 1e6}: plain FP64 against FP32 + FP64 refinement
            and BF16 + FP64 refinement (effective TFLOP/s of the whole call,
@@ -137,6 +140,37 @@ KAPPA_FAMILY_16384 = ((1e2, 0.10366329284376985, 100.5), (1e4, 0.009821718891880
                       (1e6, 0.0032196784442513815, 959245.0))
 
 
+def row_sides():
+    """f2: every flag combination at n = 8192 with 8192 right-hand sides (the
+    right side solves X op(A) = B with B of 8192 rows), and the triangular
+    product (redsea_trmm) on both methods, TFLOP/s of n^2 nrhs."""
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    n = nrhs = 8192
+    L = synth.dominant_lower(n, (1, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+    dL = rs.fortran_tensor(L)
+    dU = rs.fortran_tensor(np.asfortranarray(L.T))
+    dB0 = rs.fortran_tensor(B)
+    dB = dB0.t().clone().t()
+    flops = float(n) * n * nrhs
+    out = {"row": "sides", "n": n, "nrhs": nrhs}
+    for side in ("L", "R"):
+        for uplo, A in (("L", dL), ("U", dU)):
+            for trans in ("N", "T"):
+                ms = _time(lambda: rs.trsm(A, dB, side, uplo, trans, "N", variant="recursive", nb=256),
+                           lambda: dB.copy_(dB0), 5)
+                out["trsm_%s%s%s_tflops" % (side, uplo, trans)] = round(flops / (ms * 1e-3) / 1e12, 2)
+    dC = dB0.t().clone().t()
+    for method in ("mfma", "int8"):
+        ms = _time(lambda: rs.trmm(dL, dB0, dC, alpha=-1.0, beta=1.0, method=method),
+                   lambda: dC.copy_(dB0), 5)
+        out["trmm_%s_ms" % method] = round(ms, 3)
+        out["trmm_%s_tflops" % method] = round(flops / (ms * 1e-3) / 1e12, 2)
+    _emit(out)
+
+
 def row_mixed(targets=(1e2, 1e4, 1e6), reps=3):
     import torch
     import paper_2305_19917_amd as rs
@@ -210,7 +244,8 @@ def row_batched():
         torch.cuda.empty_cache()
 
 
-ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "mixed": row_mixed,
+ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "sides": row_sides,
+        "mixed": row_mixed,
         "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched}
 
 

@@ -9,9 +9,16 @@ tuner (redsea_tune_shape) measures.  Training and inference run on the
 library's HIP kernels (redsea_mlp_grad / redsea_mlp_adam /
 redsea_mlp_forward); this module only arranges data and launches them.
 
-Features: (log2 n, log2 nrhs, dtype, log10 kappa, log2 batch); targets: the
-natural log of the measured milliseconds of each of the 45 candidates, with a
-mask for candidates that do not apply (refinement for FP32 data).
+Features: (log2 n, log2 nrhs, dtype, log10 kappa); targets: the natural log
+of the measured milliseconds of each of the 45 candidates, with a mask for
+candidates that do not apply (refinement for FP32 data).  kappa is what an
+AUTO solve uses: the caller's estimate when it gives one, else the ratio of
+the largest to the smallest diagonal entry, which the library computes.  A
+record of a constant-diagonal (conditioning) class therefore trains twice:
+with its nominal kappa (a caller who knows it) and with kappa 1 (its
+diagonal ratio, a caller who does not).  Records carry the device name and
+the library's build id (its version string), and a database only resumes
+records of the same device and build.
 """
 from __future__ import annotations
 
@@ -42,34 +49,47 @@ def candidate(idx: int):
 
 
 def kappa_of_class(n: int, c: float, kappa: Optional[float]) -> float:
-    """Feature value of a class: its nominal kappa, or ~4.5 n for dominant."""
-    return kappa if kappa else 4.5 * n
+    """Feature value of a class as its caller would give it: the nominal kappa
+    of a conditioning class, or the diagonal ratio of a dominant matrix."""
+    return kappa if kappa else diag_ratio(n, c)
 
 
-def features(n, nrhs, dtype, kappa, batch=1):
+def diag_ratio(n: int, c: float) -> float:
+    """max |a_ii| / min |a_ii| of the tuner's generated matrices: 1 for the
+    constant diagonal of a conditioning class; for the dominant ones the
+    diagonal 1 + sum |row| runs from 1 (row 0) to about 1 + (n - 1) / 2."""
+    return 1.0 if c > 0 else 1.0 + (n - 1) / 2.0
+
+
+def features(n, nrhs, dtype, kappa):
     return [math.log2(max(n, 1)), math.log2(max(nrhs, 1)), float(dtype),
-            math.log10(max(kappa, 1.0)), math.log2(max(batch, 1))]
+            math.log10(max(kappa, 1.0))]
 
 
 # ------------------------------------------------------------------ tuning
 
 def tune(dtype: int, n: int, nrhs: int, c: float, seed: int, reps: int = 2, stream=None):
-    """Milliseconds of every candidate for one generated shape (-1 = n/a)."""
-    cand = (ctypes.c_int * NCAND)(*range(NCAND))
+    """Milliseconds of every candidate for one generated shape (-1 = n/a).
+    The library's default schedule is timed first, so that candidates far
+    behind it are cut short from the start."""
+    default = 3 * NB_CHOICES.index(256 if n > 128 else 128)
+    order = [default] + [i for i in range(NCAND) if i != default]
+    cand = (ctypes.c_int * NCAND)(*order)
     ms = (ctypes.c_double * NCAND)()
     rc = B.lib().redsea_tune_shape(dtype, n, nrhs, float(c), ctypes.c_uint64(seed), reps, cand,
                                    NCAND, ms, B._stream(stream) if stream is not None else None)
     if rc != 0:
         raise B.RedseaError(rc, B.status_string(rc))
-    return [float(x) for x in ms]
+    out = [0.0] * NCAND
+    for pos, idx in enumerate(order):
+        out[idx] = float(ms[pos])
+    return out
 
 
 # training range: orders and right-hand-side counts log-uniform in these
-# intervals (narrower than the n <= 32768, nrhs <= 16384 a full sweep would
-# cover, so that timing every candidate of ~2000 shapes fits the GPU time
-# available; the picker reports low confidence outside it)
-N_RANGE = (64, 8192)
-NRHS_RANGE = (1, 4096)
+# intervals (the picker reports low confidence outside it)
+N_RANGE = (64, 32768)
+NRHS_RANGE = (1, 16384)
 
 
 def sample_shapes(count: int, seed: int, n_range=N_RANGE, nrhs_range=NRHS_RANGE,
@@ -85,15 +105,22 @@ def sample_shapes(count: int, seed: int, n_range=N_RANGE, nrhs_range=NRHS_RANGE,
             zip(n, k, dt, cls)]
 
 
+def device_and_build():
+    import torch
+    return torch.cuda.get_device_name(0), B.version()
+
+
 def build_db(path: str, shapes: Sequence[Dict], seed0: int, reps: int = 2, log=print):
     """Time every candidate of every shape, appending JSON lines to `path`;
-    shapes already present (same n, nrhs, dtype, class) are skipped, so an
-    interrupted run resumes."""
+    shapes already present for this device and library build (same n, nrhs,
+    dtype, class) are skipped, so an interrupted run resumes."""
+    dev, build = device_and_build()
     done = set()
     if os.path.exists(path):
         for line in open(path):
             d = json.loads(line)
-            done.add((d["n"], d["nrhs"], d["dtype"], d["cls"]))
+            if d.get("device") == dev and d.get("build") == build:
+                done.add((d["n"], d["nrhs"], d["dtype"], d["cls"]))
     with open(path, "a") as f:
         for i, s in enumerate(shapes):
             key = (s["n"], s["nrhs"], s["dtype"], s["cls"])
@@ -102,7 +129,8 @@ def build_db(path: str, shapes: Sequence[Dict], seed0: int, reps: int = 2, log=p
             c, kap = KAPPA_CLASSES[s["cls"]]
             t0 = time.time()
             ms = tune(s["dtype"], s["n"], s["nrhs"], c, seed0 + i, reps)
-            rec = dict(s, c=c, kappa=kappa_of_class(s["n"], c, kap), ms=ms)
+            rec = dict(s, c=c, kappa=kappa_of_class(s["n"], c, kap),
+                       kappa_diag=diag_ratio(s["n"], c), device=dev, build=build, ms=ms)
             f.write(json.dumps(rec) + "\n")
             f.flush()
             done.add(key)
@@ -111,8 +139,13 @@ def build_db(path: str, shapes: Sequence[Dict], seed0: int, reps: int = 2, log=p
                 min(x for x in ms if x > 0), time.time() - t0))
 
 
-def load_db(path: str):
+def load_db(path: str, training: bool = False):
+    """Features, log-ms targets, masks and times of a database.  With
+    `training`, a conditioning-class record appears twice (nominal kappa and
+    diagonal-ratio kappa); otherwise once, with the kappa its caller gives."""
     recs = [json.loads(l) for l in open(path) if l.strip()]
+    if training:
+        recs = recs + [dict(r, kappa=r.get("kappa_diag", 1.0)) for r in recs if r["cls"] > 0]
     X = np.array([features(r["n"], r["nrhs"], r["dtype"], r["kappa"]) for r in recs], np.float64)
     ms = np.array([r["ms"] for r in recs], np.float64)
     mask = (ms > 0).astype(np.float64)
@@ -152,7 +185,7 @@ class Net:
     def save(self, path):
         P = self.p.cpu().numpy()
         with open(path, "w") as f:
-            f.write("redsea-mlp 1\n5 64 64 45\n")
+            f.write("redsea-mlp 2\n%d 64 64 45\n" % len(self.mu))
             f.write(" ".join("%.9g" % v for v in self.mu) + "\n")
             f.write(" ".join("%.9g" % v for v in self.sd) + "\n")
             f.write("%.9g %.9g %.9g %.9g\n" % (self.lo[0], self.hi[0], self.lo[1], self.hi[1]))
@@ -162,18 +195,19 @@ class Net:
     @staticmethod
     def load(path):
         tok = open(path).read().split()
-        assert tok[0] == "redsea-mlp" and tok[1] == "1"
+        assert tok[0] == "redsea-mlp" and tok[1] == "2"
+        nin = int(tok[2])
         vals = [float(t) for t in tok[6:]]
-        mu, sd = vals[0:5], vals[5:10]
-        lo = [vals[10], vals[12]]
-        hi = [vals[11], vals[13]]
-        return Net(mu, sd, lo, hi, params=np.array(vals[14:], np.float32))
+        mu, sd = vals[0:nin], vals[nin:2 * nin]
+        lo = [vals[2 * nin], vals[2 * nin + 2]]
+        hi = [vals[2 * nin + 1], vals[2 * nin + 3]]
+        return Net(mu, sd, lo, hi, params=np.array(vals[2 * nin + 4:], np.float32))
 
 
 def init_params(seed=0):
     """He-style initialisation, packed W1, b1, W2, b2, W3, b3."""
     r = np.random.default_rng([5, seed])
-    sizes = (5, 64, 64, 45)
+    sizes = (4, 64, 64, 45)
     out = []
     for a, b in zip(sizes[:-1], sizes[1:]):
         out.append(r.normal(0, math.sqrt(2.0 / a), (b, a)).ravel())
@@ -274,6 +308,44 @@ def leaf_table(nrhs_grid=(1, 4, 16, 64, 256, 1024, 4096, 8192), reps=5, seed=99)
     return out
 
 
+def gemm_table(mks=(32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
+               ns=(1, 4, 16, 64, 256, 1024, 4096, 16384), reps=5):
+    """Milliseconds of the FP64 product update C -= A X (M = K = mk, N = n) on
+    the library's default tiles, and the launch latency (a 16 x 16 x 16
+    product, 200 back to back), for the analytic model's gemm term."""
+    import torch
+    entries = []
+    r = np.random.default_rng(7)
+    for mk in mks:
+        A = torch.tensor(r.uniform(-1, 1, (mk, mk)), device="cuda").t()
+        for n in ns:
+            X = torch.tensor(r.uniform(-1, 1, (n, mk)), device="cuda").t()
+            C = torch.zeros((mk, n), dtype=torch.float64, device="cuda").t().contiguous().t()
+            B.gemm_update(A, X, C)
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                B.gemm_update(A, X, C)
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            entries.append({"mk": mk, "n": n, "ms": sorted(times)[len(times) // 2]})
+            del X, C
+        del A
+        torch.cuda.empty_cache()
+    a = torch.ones((16, 16), dtype=torch.float64, device="cuda").t()
+    c = torch.zeros((16, 16), dtype=torch.float64, device="cuda").t()
+    B.gemm_update(a, a, c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        B.gemm_update(a, a, c)
+    e1.record()
+    e1.synchronize()
+    return {"entries": entries, "launch_ms": e0.elapsed_time(e1) / 200}
+
+
 def _tune_one(dtype, n, nrhs, idx, seed, reps):
     cand = (ctypes.c_int * 1)(idx)
     ms = (ctypes.c_double * 1)()
@@ -297,6 +369,8 @@ def main(argv=None):
     a.add_argument("--max-seconds", type=float, default=0.0)
     b = sub.add_parser("leaf-table", help="leaf times for the paper's refinement rule")
     b.add_argument("--out", required=True)
+    g = sub.add_parser("gemm-table", help="product times for the paper's analytic model")
+    g.add_argument("--out", required=True)
     c = sub.add_parser("train", help="train the network on a database")
     c.add_argument("--db", required=True)
     c.add_argument("--out", required=True)
@@ -306,6 +380,7 @@ def main(argv=None):
     d.add_argument("--db", required=True)
     d.add_argument("--weights", required=True)
     d.add_argument("--leaf-table", default=None)
+    d.add_argument("--gemm-table", default=None)
     d.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "build-db":
@@ -324,8 +399,12 @@ def main(argv=None):
         json.dump({str(k): {str(nb): v for nb, v in row.items()} for k, row in tab.items()},
                   open(args.out, "w"), indent=1)
         print(json.dumps(tab))
+    elif args.cmd == "gemm-table":
+        tab = gemm_table()
+        json.dump(tab, open(args.out, "w"), indent=1)
+        print(json.dumps(tab))
     elif args.cmd == "train":
-        recs, X, T, mask, ms = load_db(args.db)
+        recs, X, T, mask, ms = load_db(args.db, training=True)
         net, hist = train(X, T, mask, epochs=args.epochs, seed=args.seed, log=print)
         net.save(args.out)
         pred = net.predict(X)
@@ -340,7 +419,7 @@ def main(argv=None):
         res = {"heldout_shapes": len(recs), "mlp_regret": summary(reg),
                "mlp_total_ms": float(ms[np.arange(len(ms)), pick].sum()),
                "best_total_ms": float(np.min(np.where(mask > 0, ms, np.inf), axis=1).sum())}
-        fixed = 3 * NB_CHOICES.index(128)  # recursive, nb 128, native
+        fixed = 3 * NB_CHOICES.index(256)  # the library default: recursive, nb 256, native
         res["fixed_default_total_ms"] = float(ms[:, fixed].sum())
         if args.leaf_table:
             tab = {int(k): {int(nb): v for nb, v in row.items()}
@@ -350,6 +429,14 @@ def main(argv=None):
             res["paper_rule_regret"] = summary(breg)
             res["paper_rule_total_ms"] = float(ms[np.arange(len(ms)), bp].sum())
             res["mlp_gain_over_paper_rule"] = res["paper_rule_total_ms"] / res["mlp_total_ms"]
+            if args.gemm_table:
+                from . import costmodel
+                cm = costmodel.load(json.load(open(args.leaf_table)), json.load(open(args.gemm_table)))
+                ap = np.array([costmodel.pick(r["n"], r["nrhs"], cm) for r in recs])
+                areg = ms[np.arange(len(ms)), ap] / np.min(np.where(mask > 0, ms, np.inf), axis=1) - 1
+                res["analytic_model_regret"] = summary(areg)
+                res["analytic_model_total_ms"] = float(ms[np.arange(len(ms)), ap].sum())
+                res["mlp_gain_over_analytic_model"] = res["analytic_model_total_ms"] / res["mlp_total_ms"]
         print(json.dumps(res, indent=1))
         if args.out:
             json.dump(res, open(args.out, "w"), indent=1)

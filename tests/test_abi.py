@@ -31,7 +31,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_status_strings():
-    assert re.match(r"^\d+\.\d+\.\d+$", rs.version())
+    assert re.match(r"^\d+\.\d+\.\d+\+[0-9a-f]{12}$", rs.version())
+    from paper_2305_19917_amd import build
+    assert rs.version().endswith(build.build_id())
     assert rs.status_string(0) == "success"
     assert "invalid" in rs.status_string(-3)
     for code in range(1, 6):

@@ -10,7 +10,7 @@ from oracle import mlp
 def _data(seed, nb=16):
     r = np.random.default_rng([50, seed])
     p = r.normal(0, 0.3, mlp.count())
-    X = r.normal(0, 1, (nb, 5))
+    X = r.normal(0, 1, (nb, 4))
     T = r.normal(0, 1, (nb, 45))
     mask = (r.uniform(size=(nb, 45)) < 0.8).astype(float)
     return p, X, T, mask
@@ -31,10 +31,10 @@ def test_gradient_matches_finite_differences(seed):
 
 
 def test_layout_and_count():
-    assert mlp.count() == 5 * 64 + 64 + 64 * 64 + 64 + 45 * 64 + 45
+    assert mlp.count() == 4 * 64 + 64 + 64 * 64 + 64 + 45 * 64 + 45
     p = np.arange(mlp.count(), dtype=float)
     W1, b1, W2, b2, W3, b3 = mlp.unpack(p)
-    assert W1.shape == (64, 5) and W1[0, 1] == 1 and b1[0] == 320
+    assert W1.shape == (64, 4) and W1[0, 1] == 1 and b1[0] == 256
     assert W3.shape == (45, 64) and b3[-1] == mlp.count() - 1
 
 

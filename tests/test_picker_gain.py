@@ -1,0 +1,66 @@
+"""What the trained picker gains over the methods without it, on the stored
+held-out timings (every one of the 45 candidates timed on each held-out shape
+by the library's exhaustive tuner), on the CPU: the library's own host
+inference (redsea_pick, the same code AUTO solves run) picks a candidate for
+each shape, and its summed time is compared with
+* the refinement rule of Sec. V-A (recursive, native precision, the leaf
+  halved while two half-size leaves are faster than one, from measured leaf
+  times), the baseline the network replaces;
+* the paper's analytic latency model (Sec. V Comp + Comm), refitted to
+  measured leaf and product times;
+* the library's default schedule (recursive, nb 256, native precision).
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2305_19917_amd as rs
+from paper_2305_19917_amd import costmodel, picker
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                    "paper_2305_19917_amd", "data")
+HELD = os.path.join(DATA, "tune_heldout.jsonl")
+LEAF = os.path.join(DATA, "leaf_table.json")
+GEMM = os.path.join(DATA, "gemm_table.json")
+# required gains of the learned picker in summed held-out time
+MIN_GAIN_OVER_RULE = 1.15
+MIN_GAIN_OVER_MODEL = 1.05
+MIN_GAIN_OVER_DEFAULT = 1.05
+MAX_MEAN_REGRET = 0.10
+
+
+def _totals():
+    recs, X, T, mask, ms = picker.load_db(HELD)
+    L = rs.lib()
+    conf = ctypes.c_int()
+    mlp = np.array([L.redsea_pick(r["dtype"], r["n"], r["nrhs"], float(r["kappa"]),
+                                  ctypes.byref(conf)) for r in recs])
+    assert np.all(mlp >= 0), "no trained weights loaded"
+    rows = np.arange(len(recs))
+    best = np.min(np.where(mask > 0, ms, np.inf), axis=1)
+    leaf = {int(k): {int(nb): v for nb, v in row.items()} for k, row in json.load(open(LEAF)).items()}
+    rule = np.array([picker.paper_rule_pick(r["n"], r["nrhs"], leaf) for r in recs])
+    cm = costmodel.load(json.load(open(LEAF)), json.load(open(GEMM)))
+    model = np.array([costmodel.pick(r["n"], r["nrhs"], cm) for r in recs])
+    default = np.full(len(recs), 3 * picker.NB_CHOICES.index(256))
+    tot = {name: float(ms[rows, pick].sum()) for name, pick in
+           (("mlp", mlp), ("rule", rule), ("model", model), ("default", default))}
+    tot["best"] = float(best.sum())
+    reg = ms[rows, mlp] / best - 1.0
+    return tot, reg
+
+
+@pytest.mark.skipif(not all(os.path.exists(p) for p in (HELD, LEAF, GEMM)),
+                    reason="timing data not generated")
+def test_learned_picker_gains_over_the_methods_without_it():
+    tot, reg = _totals()
+    print("held-out totals (ms):", json.dumps({k: round(v, 2) for k, v in tot.items()}),
+          "mlp regret mean %.4f p90 %.4f" % (reg.mean(), np.percentile(reg, 90)))
+    assert tot["rule"] / tot["mlp"] >= MIN_GAIN_OVER_RULE
+    assert tot["model"] / tot["mlp"] >= MIN_GAIN_OVER_MODEL
+    assert tot["default"] / tot["mlp"] >= MIN_GAIN_OVER_DEFAULT
+    assert reg.mean() <= MAX_MEAN_REGRET
+    assert tot["mlp"] >= tot["best"]

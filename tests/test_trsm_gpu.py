@@ -332,3 +332,20 @@ def test_graph_capture_is_refused_not_dangling():
     assert code == 5
     X = gpu_solve(L, B, variant="recursive", nb=128)
     assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
+
+
+@pytest.mark.parametrize("k,nrhs,nb", [(8192, 64, 256), (3000, 500, 256), (2048, 333, 128),
+                                       (1000, 100, 64)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_lookahead_changes_no_bit(k, nrhs, nb, dtype, monkeypatch):
+    """Look-ahead (the rows of a product beyond the next leaf updated on a
+    helper stream while that leaf runs) gives exactly the bits of the
+    sequential order."""
+    L = synth.dominant_lower(k, (24, k, 0))
+    B = synth.rhs_normal(k, nrhs, (24, k, 1))
+    for variant in ("recursive", "iterative"):
+        monkeypatch.setenv("REDSEA_LOOKAHEAD", "0")
+        X0 = gpu_solve(L, B, variant=variant, nb=nb, dtype=dtype)
+        monkeypatch.setenv("REDSEA_LOOKAHEAD", "1")
+        X1 = gpu_solve(L, B, variant=variant, nb=nb, dtype=dtype)
+        assert np.array_equal(X0, X1), (variant, dtype)
