@@ -443,7 +443,26 @@ size_t packed_bytes(const Canon& c, int64_t nb) {
     return (size_t)nblk * leaf_block_elems((int)kleaf) * es;
 }
 
+// Recursive solves with at most this many right-hand sides run as one
+// dataflow launch (k_thin.hip) when the library owns the memory;
+// REDSEA_THIN=0 turns that off.
+constexpr int64_t kThinMaxRhs = 64;
+
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed) {
+    if (variant == VAR_RECURSIVE && !packed && !c.gemm_bf16 && c.nrhs <= kThinMaxRhs) {
+        const char* env = std::getenv("REDSEA_THIN");
+        if (!(env && std::atoi(env) == 0)) {
+            WsLease fl;
+            int rc = workspace(6, (size_t)thin_flag_count(c.k) * sizeof(int), s, fl);
+            if (rc) return rc;
+            const hipError_t e = traced(REDSEA_KERNEL_LEAF, (double)c.k * c.k * c.nrhs, s, [&] {
+                return launch_thin(c.dtype, c.tri, c.rhs, c.k, c.nrhs, c.unit, (int*)fl.ptr, s);
+            });
+            if (e == hipSuccess) return REDSEA_OK;
+            if (e != hipErrorCooperativeLaunchTooLarge) return REDSEA_ERR_HIP;
+            (void)hipGetLastError();  // more blocks than resident workgroups: the split below
+        }
+    }
     const int64_t kleaf = leaf_rows(nb);
     const std::vector<Task>& tasks = plan_for(variant, c.k, nb, kleaf);
     const int64_t nblk = (c.k + kleaf - 1) / kleaf;

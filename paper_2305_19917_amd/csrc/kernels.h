@@ -90,6 +90,16 @@ hipError_t launch_scale(int dtype, void* b, int64_t m, int64_t n, int64_t ldb, d
 hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* out,
                                 hipStream_t s);
 
+// The whole canonical solve for at most 64 right-hand sides as one
+// persistent dataflow launch (cooperative: every 64-row block's workgroup
+// resident at once; blocks wait on readiness flags in `flags`, which must
+// hold thin_flag_count(n) ints of device memory).  Returns
+// hipErrorCooperativeLaunchTooLarge, with nothing launched, when the device
+// cannot hold all blocks at once.
+int64_t thin_flag_count(int64_t n);
+hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t ncols,
+                       bool unit, int* flags, hipStream_t s);
+
 // info[0] := 0 if every entry of the m x n matrix is finite, else `code`.
 hipError_t launch_check_finite(int dtype, const void* b, int64_t m, int64_t n, int64_t ldb,
                                int* info, int code, hipStream_t s);

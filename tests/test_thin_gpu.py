@@ -1,0 +1,105 @@
+"""The one-launch dataflow solve for thin right-hand sides (at most 64, the
+recursive schedule) against the CPU oracle: normwise backward error
+<= 1e-14 n with the oracle's compensated residual, bitwise results where the
+answer is exact, run-to-run determinism, the split schedule's fallback when
+the blocks exceed the resident workgroups."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2305_19917_amd as rs
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+FLAGS = list(itertools.product([0, 1], [0, 1], [0, 1], [0, 1]))
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _solve(A, B, side=0, uplo=0, trans=0, diag=0, alpha=1.0, dtype=np.float64, thin=True,
+           monkeypatch=None):
+    if monkeypatch is not None:
+        monkeypatch.setenv("REDSEA_THIN", "1" if thin else "0")
+    dA = rs.fortran_tensor(np.asarray(A, dtype=dtype))
+    dB = rs.fortran_tensor(np.asarray(B, dtype=dtype))
+    rs.trsm(dA, dB, side=side, uplo=uplo, trans=trans, diag=diag, alpha=alpha, variant="recursive",
+            nb=256)
+    torch.cuda.synchronize()
+    return dB.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("k", [1, 63, 64, 100, 1000, 4097])
+@pytest.mark.parametrize("nrhs", [1, 7, 16, 33, 64])
+def test_thin_backward_error(k, nrhs):
+    L = synth.dominant_lower(k, (50, k, 0))
+    B = synth.rhs_normal(k, nrhs, (50, nrhs, 1))
+    X = _solve(L, B)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * max(k, 1)
+    assert oracle.forward_error(X, oracle.trsm_plain(0, 0, 0, 0, 1.0, L, B)) <= 1e-11
+
+
+@pytest.mark.parametrize("side,uplo,trans,diag", FLAGS)
+def test_thin_all_flags(side, uplo, trans, diag):
+    k, nrhs = 777, 19
+    L = synth.unit_lower(k, (51, k, 0)) if diag else synth.dominant_lower(k, (51, k, 0))
+    A = np.array(L if uplo == 0 else L.T, order="F")
+    A[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    B = synth.rhs_normal(*((k, nrhs) if side == 0 else (nrhs, k)), key=(51, k, 1))
+    X = _solve(A, B, side, uplo, trans, diag, alpha=-0.5)
+    assert oracle.backward_error(side, uplo, trans, diag, -0.5, A, B, X) <= 1e-14 * k
+
+
+def test_thin_fp32_and_exact_cases():
+    k, nrhs = 1500, 40
+    L = synth.dominant_lower(k, (52, 0, 0)).astype(np.float32).astype(np.float64)
+    B = synth.rhs_normal(k, nrhs, (52, 0, 1)).astype(np.float32).astype(np.float64)
+    X = _solve(L, B, dtype=np.float32)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 5e-6 * k
+    # integer systems come out exact; a diagonal system divides exactly
+    for side, uplo, trans, diag in [(0, 0, 0, 0), (0, 1, 1, 1), (1, 0, 0, 0), (1, 1, 1, 1)]:
+        m, n = (300, 20) if side == 0 else (20, 300)
+        A, Bi, Xt = synth.integer_exact(m, n, (53, side, uplo), side, uplo, trans, diag)
+        assert np.array_equal(_solve(A, Bi, side, uplo, trans, diag), Xt)
+    D = synth.diagonal(500, (54, 0, 0))
+    Bd = synth.rhs_normal(500, 9, (54, 0, 1))
+    assert np.array_equal(_solve(D, Bd), Bd / np.diag(D)[:, None])
+
+
+@pytest.mark.parametrize("nrhs", [1, 8, 32])
+def test_thin_config1_order_sampled(nrhs):
+    n = 8192
+    L = synth.dominant_lower(n, (1, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+    X = _solve(L, B)
+    eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X)
+    _say("thin n=8192 nrhs=%d eta %.2e" % (nrhs, eta))
+    assert eta <= 1e-14 * n
+    X2 = _solve(L, B)
+    assert np.array_equal(X, X2)  # run to run
+
+
+def test_thin_matches_split_schedule_within_rounding(monkeypatch):
+    k, nrhs = 3000, 24
+    L = synth.dominant_lower(k, (55, 0, 0))
+    B = synth.rhs_normal(k, nrhs, (55, 0, 1))
+    X1 = _solve(L, B, monkeypatch=monkeypatch, thin=True)
+    X0 = _solve(L, B, monkeypatch=monkeypatch, thin=False)
+    for X in (X0, X1):
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
+    assert oracle.forward_error(X1, X0) <= 1e-12
+
+
+def test_more_blocks_than_resident_workgroups_fall_back():
+    # 20000 rows = 313 blocks of 64: more than one workgroup per CU can hold
+    # at once on 256 CUs, so the split schedule solves it
+    k, nrhs = 20000, 3
+    L = synth.dominant_lower(k, (56, 0, 0))
+    B = synth.rhs_normal(k, nrhs, (56, 0, 1))
+    X = _solve(L, B)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
