@@ -134,7 +134,8 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * solve as redsea_trsm (same arguments, numbers and kernels; for a given
  * variant and nb the result is bitwise that of redsea_trsm) in native
- * precision only, with its scratch memory (the packed diagonal blocks) in a
+ * precision only, with its scratch memory (the packed diagonal blocks, or
+ * the flags of the one-launch solve for thin right-hand sides) in a
  * fixed device array of REDSEA_NOALLOC_SCRATCH_BYTES that the library holds
  * on each device it runs on until the process ends.  It calls no hipMalloc,
  * hipFree or other allocating routine and never waits for the device, so it
@@ -343,7 +344,8 @@ enum {
     REDSEA_KERNEL_LEAF = 1,       /* leaf solve (Sec. V white triangles) */
     REDSEA_KERNEL_GEMM = 2,       /* one product update (grey rectangle) */
     REDSEA_KERNEL_GEMM_GROUP = 3, /* one blocked round of products       */
-    REDSEA_KERNEL_CLASSES = 4
+    REDSEA_KERNEL_THIN = 4,       /* whole solve as one dataflow launch  */
+    REDSEA_KERNEL_CLASSES = 5
 };
 void redsea_trace_begin(void);
 int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds);

@@ -42,7 +42,7 @@ EXPORTS = (
     "redsea_mlp_load",
     "redsea_mfma_peak",
 )
-KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group")
+KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group", "thin")
 
 SIDE = {"L": 0, "R": 1, 0: 0, 1: 1}
 UPLO = {"L": 0, "U": 1, 0: 0, 1: 1}

@@ -443,20 +443,34 @@ size_t packed_bytes(const Canon& c, int64_t nb) {
     return (size_t)nblk * leaf_block_elems((int)kleaf) * es;
 }
 
-// Recursive solves with at most this many right-hand sides run as one
-// dataflow launch (k_thin.hip) when the library owns the memory;
-// REDSEA_THIN=0 turns that off.
+// Recursive solves with few right-hand sides run as one dataflow launch
+// (k_thin.hip) when the library owns the memory.  Measured on MI355X (FP64,
+// diagonally dominant lower triangle), the launch beats both the split
+// recursive and the iterative schedules for at most 16 right-hand sides at
+// every order from 512 to 8192 (n = 8192, one right-hand side: 0.47 ms
+// against 1.58 ms iterative and 2.59 ms split) and for at most 32 from
+// n = 2048 on; with 64 the split schedules are as fast or faster.
+// REDSEA_THIN=1 takes the launch for any count up to its limit of 64,
+// REDSEA_THIN=0 never.
 constexpr int64_t kThinMaxRhs = 64;
 
-int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed) {
-    if (variant == VAR_RECURSIVE && !packed && !c.gemm_bf16 && c.nrhs <= kThinMaxRhs) {
+bool thin_pays(int64_t n, int64_t nrhs) { return nrhs <= 16 || (nrhs <= 32 && n >= 2048); }
+
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed,
+            int* thin_flags) {
+    if (variant == VAR_RECURSIVE && (!packed || thin_flags) && !c.gemm_bf16 &&
+        c.nrhs <= kThinMaxRhs) {
         const char* env = std::getenv("REDSEA_THIN");
-        if (!(env && std::atoi(env) == 0)) {
+        const int mode = env ? std::atoi(env) : -1;  // -1: by the measured crossover
+        if (mode == 1 || (mode != 0 && thin_pays(c.k, c.nrhs))) {
             WsLease fl;
-            int rc = workspace(6, (size_t)thin_flag_count(c.k) * sizeof(int), s, fl);
-            if (rc) return rc;
-            const hipError_t e = traced(REDSEA_KERNEL_LEAF, (double)c.k * c.k * c.nrhs, s, [&] {
-                return launch_thin(c.dtype, c.tri, c.rhs, c.k, c.nrhs, c.unit, (int*)fl.ptr, s);
+            if (!packed) {
+                int rc = workspace(6, (size_t)thin_flag_count(c.k) * sizeof(int), s, fl);
+                if (rc) return rc;
+                thin_flags = (int*)fl.ptr;
+            }
+            const hipError_t e = traced(REDSEA_KERNEL_THIN, (double)c.k * c.k * c.nrhs, s, [&] {
+                return launch_thin(c.dtype, c.tri, c.rhs, c.k, c.nrhs, c.unit, thin_flags, s);
             });
             if (e == hipSuccess) return REDSEA_OK;
             if (e != hipErrorCooperativeLaunchTooLarge) return REDSEA_ERR_HIP;

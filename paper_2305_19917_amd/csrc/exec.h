@@ -50,7 +50,11 @@ int workspace(int slot, size_t bytes, hipStream_t s, WsLease& out);
 size_t packed_bytes(const Canon& c, int64_t nb);
 // Runs the solve on stream s.  packed: device memory of packed_bytes(c, nb)
 // bytes for the diagonal blocks, or null to take it from the workspace.
-int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed = nullptr);
+// thin_flags: device memory of thin_flag_count ints for the one-launch thin
+// solve when `packed` is given (without it, a caller-owned-memory solve
+// takes the split schedule); ignored when packed is null.
+int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed = nullptr,
+            int* thin_flags = nullptr);
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
 int pick_nb(int requested, int64_t k);

@@ -7,7 +7,7 @@
 // (64 rows) belongs to workgroup i of a cooperative launch (all workgroups
 // resident at once).  The workgroup starts from its rows of B and, for j = 0,
 // 1, ..., i - 1, waits until block j is solved (a readiness flag in global
-// memory, agent-scope acquire / release atomics), stages X_j in LDS and
+// memory, device-coherent accesses), stages X_j in LDS and
 // subtracts L_ij X_j on the matrix cores (v_mfma_f64_16x16x4f64, one 16-row
 // slice of the block per wave).  Then it solves its 64 x 64 diagonal block by
 // substitution in axpy order, one lane per right-hand side, each unknown the
@@ -22,6 +22,7 @@
 // workgroup sees the abort flag and does the same, so the launch always ends.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "fdiv.h"
@@ -34,12 +35,37 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTB = 64;     // rows per block
 constexpr int kTCols = 64;  // right-hand sides at most
+constexpr int kAbortAt = 32;  // flags index of the abort flag (128 bytes on)
+constexpr int kMaxDevices = 64;
+constexpr int kStager = 4;             // the wave that waits for and stages solved blocks
+constexpr int kThreads = 64 * (kStager + 1);
 
-__device__ __forceinline__ int flag_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Solved blocks travel through agent-scope stores and loads (written
+// through to memory; a consumer's L2 never holds a line of X_j from before
+// it was solved, since only block j's own workgroup reads those rows
+// earlier).  Flags are read and raised with agent-scope read-modify-write
+// atomics, which every XCD sees at once; a plain or agent-scope load of a
+// flag can keep returning the consumer XCD's stale copy of its line until
+// that line is evicted.  Acquire / release operations would be correct too,
+// but their cache maintenance (an L2 invalidation per poll) is slower.  A
+// block's stores are complete (waited for, then a workgroup barrier) before
+// its flag is raised, and a consumer loads the block only after it has seen
+// the flag.
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void flag_release(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+template <typename T>
+__device__ __forceinline__ void coherent_store(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// `zero` is a kernel argument equal to 0, so the compiler cannot turn the
+// read-modify-write into a plain load
+__device__ __forceinline__ int flag_read(int* p, int zero) {
+    return __hip_atomic_fetch_add(p, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_raise(int* p) {
+    __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void thin_flags_kernel(int* flags, int64_t count) {
@@ -48,168 +74,326 @@ __global__ void thin_flags_kernel(int* flags, int64_t count) {
         flags[i] = 0;
 }
 
-// flags[0 .. nblk) readiness, flags[nblk] abort.
-template <typename T, bool UNIT, int NCG>
-__global__ __launch_bounds__(256, 1) void thin_kernel(TriView L, RhsView B, int64_t n, int ncols,
-                                                      int* flags, int64_t spin_limit) {
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// a / d correctly rounded (the fast form where its guard holds; the IEEE
+// division only on the rare lanes where it does not)
+__device__ __forceinline__ double div_rn(double a, double d, double r) {
+    bool ok;
+    double q = div_rn_fast(a, d, r, div_fast_divisor(d), ok);
+    if (__builtin_expect(!ok, 0)) q = a / d;
+    return q;
+}
+
+// flags[0]: the number of solved blocks (blocks finish in order, each
+// needing its predecessor); flags[kAbortAt]: abort, in a cache line of its
+// own.  Waves 0-3 own the block's rows; wave 4 (kStager) waits for solved
+// blocks and stages them in LDS.  CPW > 0: the diagonal block's substitution
+// runs with its rows across the lanes, CPW right-hand sides per wave;
+// CPW = 0: in 16-row steps with one lane per right-hand side.
+template <typename T, bool UNIT, int NCG, int CPW>
+__global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B, int64_t n,
+                                                           int ncols, int* flags,
+                                                           int64_t spin_limit, int zero) {
+    constexpr int kXPer = kTB * 16 * NCG / 256;  // elements of a row block per row thread
+    constexpr bool ROWPAR = CPW > 0;
     __shared__ double Xs[kTB][kTCols + 2];  // X_j of an update, then this block's rows
-    __shared__ double Ls[kTB][kTB + 1];     // the diagonal block, Ls[row][col]
-    __shared__ double Rs[kTB];              // 1 / diagonal
-    __shared__ int s_go;
+    __shared__ double Ls[kTB][kTB + 1];     // D^-1 L_ii strictly below the diagonal, else zero
+    __shared__ double Ds[kTB], Rs[kTB];     // the diagonal and its reciprocals
+    __shared__ int s_abort;
     const T* A = (const T*)L.base;
     T* Bp = (T*)B.base;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
-    const int64_t nblk = (n + kTB - 1) / kTB;
+    // the wave index as a wave-uniform value: every branch on it is a scalar
+    // branch, so a wave runs only its own role's code (no exec-masked pass
+    // through the other's barriers and memory waits)
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool rows_wave = w < kStager;  // waves 0-3
     const int64_t i = blockIdx.x;
     const int64_t r0 = i * kTB;
     const int rows = (int)(n - r0 < kTB ? n - r0 : kTB);
-    int* abort_flag = flags + nblk;
+    int* progress = flags;
+    int* abort_flag = flags + kAbortAt;
     auto tget = [&](int64_t r, int64_t col) -> double {
         return (double)A[L.off + r * L.tr + col * L.tc];
     };
     auto bptr = [&](int64_t r, int64_t col) -> T* { return Bp + B.off + r * B.br + col * B.bc; };
 
-    // this wave's 16 rows of the block, in the accumulator layout (lane l,
-    // register r: row g + 4r, column c of column group cg)
+    // 1. Work that waits for nothing, done while earlier blocks are solved.
+    // This wave's 16 rows of the block, in the accumulator layout (lane l,
+    // register r: row g + 4r, column c of column group cg).
     v4d acc[NCG];
 #pragma unroll
     for (int cg = 0; cg < NCG; ++cg)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * w + g + 4 * r, col = 16 * cg + c;
-            acc[cg][r] = (row < rows && col < ncols) ? (double)*bptr(r0 + row, col) : 0.0;
+            acc[cg][r] = (rows_wave && row < rows && col < ncols) ? (double)*bptr(r0 + row, col) : 0.0;
         }
-
-    bool aborted = false;
-    for (int64_t j = 0; j < i; ++j) {
-        if (tid == 0) {
-            int go = 1;
-            int64_t spins = 0;
-            while (flag_acquire(flags + j) == 0) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                    ++spins > spin_limit) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    go = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            s_go = go;
-        }
-        __syncthreads();
-        if (!s_go) {  // uniform over the workgroup (read after the barrier)
-            aborted = true;
-            break;
-        }
-        // X_j into LDS (rows along consecutive threads)
-        for (int e = tid; e < kTB * 16 * NCG; e += 256) {
-            const int kk = e % kTB, col = e / kTB;
-            const int64_t gr = j * kTB + kk;
-            Xs[kk][col] = (col < ncols && gr < n) ? (double)*bptr(gr, col) : 0.0;
-        }
-        __syncthreads();
-        // acc -= L_ij X_j in 16 steps of four columns of L_ij
-        const int64_t arow = r0 + 16 * w + c;
-        const bool arow_ok = 16 * w + c < rows;
-#pragma unroll 4
-        for (int ks = 0; ks < 16; ++ks) {
-            const int64_t acol = j * kTB + 4 * ks + g;
-            const double a = (arow_ok && acol < n) ? -tget(arow, acol) : 0.0;
-#pragma unroll
-            for (int cg = 0; cg < NCG; ++cg)
-                acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Xs[4 * ks + g][16 * cg + c], acc[cg],
-                                                              0, 0, 0);
-        }
-        __syncthreads();  // Xs is overwritten next
+    // The diagonal block (the identity past the order n), each row divided
+    // by its diagonal element: the unit lower triangular D^-1 L_ii.
+    if (tid < kTB) {
+        const double d = (UNIT || tid >= rows) ? 1.0 : tget(r0 + tid, r0 + tid);
+        Ds[tid] = d;
+        Rs[tid] = 1.0 / d;
     }
-
-    // the block's right-hand sides and its diagonal block into LDS (the
-    // diagonal block is the identity past the order n)
+    if (tid == 0) s_abort = 0;
+    double dv[16];
+    if (rows_wave) {
 #pragma unroll
-    for (int cg = 0; cg < NCG; ++cg)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Xs[16 * w + g + 4 * r][16 * cg + c] = acc[cg][r];
-    for (int e = tid; e < kTB * kTB; e += 256) {
-        const int rr = e % kTB, cc = e / kTB;
-        double v = 0.0;
-        if (rr >= rows || cc >= rows) v = (rr == cc) ? 1.0 : 0.0;
-        else if (rr == cc) v = UNIT ? 1.0 : tget(r0 + rr, r0 + cc);
-        else if (rr > cc) v = tget(r0 + rr, r0 + cc);
-        Ls[rr][cc] = v;
-        if (!UNIT && rr == cc) Rs[rr] = 1.0 / v;
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k, rr = e % kTB, cc = e / kTB;
+            dv[k] = (rr < rows && cc < rr) ? tget(r0 + rr, r0 + cc) : 0.0;
+        }
     }
     __syncthreads();
-    // substitution in axpy order: wave 0, lane = right-hand side, in four
-    // 16-row steps held in registers; after a step its unknowns update the
-    // rows below (each row with the step's unknowns in increasing order).
-    // The fast divisions of a step are redone in IEEE arithmetic for the whole
-    // wave if any operand left their guard (same quotient wherever it held).
-    if (w == 0 && !aborted) {
-#pragma unroll 1
-        for (int sb = 0; sb < kTB / 16; ++sb) {
-            const int b0 = 16 * sb;
-            double y[16];
-            auto step = [&](auto fast) {
+    if (rows_wave) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) y[r] = Xs[b0 + r][lane];
-                bool ok = true;
+        for (int k = 0; k < 16; ++k) {
+            const int e = tid + 256 * k, rr = e % kTB, cc = e / kTB;
+            Ls[rr][cc] = UNIT ? dv[k] : div_rn(dv[k], Ds[rr], Rs[rr]);
+        }
+    }
+    __syncthreads();
+
+    // 2. acc -= L_ij X_j for j < i, as each block is solved.  The row waves
+    // hold the operands of L_ij (their 16 rows, 16 steps of four columns) in
+    // a ring of three register buffers, loaded two updates ahead: the loads
+    // take several microseconds, which this hides behind the block solves.
+    // The stager's queue of memory operations holds only its polls and the
+    // loads of X_j, so neither ever waits behind a load of L.
+    // The loads are unconditional and untouched until their use, so all 16
+    // stay in flight together: a row past the order n reads row n - 1
+    // instead, which only feeds accumulator rows that are never stored.
+    const int64_t arow = r0 + (16 * w + c < rows ? 16 * w + c : rows - 1);
+    auto load_a = [&](int64_t j, T(&a)[16]) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    double x = y[r];
-                    if (!UNIT) {
-                        const double d = Ls[b0 + r][b0 + r];
-                        if constexpr (decltype(fast)::value) {
-                            bool oki;
-                            x = div_rn_fast(y[r], d, Rs[b0 + r], div_fast_divisor(d), oki);
-                            ok = ok && oki;
-                        } else {
-                            x = y[r] / d;
+        for (int ks = 0; ks < 16; ++ks) a[ks] = A[L.off + arow * L.tr + (j * kTB + 4 * ks + g) * L.tc];
+    };
+    // The prefetch is unconditional (past the last update it reloads block
+    // i - 1): with a conditional one the compiler's wait before the products
+    // has to cover the path without it, and then waits for the fresh loads.
+    T ab0[16], ab1[16], ab2[16];  // L_ij is in buffer j mod 3
+    // The two roles run separate loops (a wave takes one of them by a scalar
+    // branch), each with the same two barriers per update; an abandoned wait
+    // ends both after the first.
+    bool aborted = false;
+    if (!rows_wave) {
+        int64_t known = 0;  // blocks known to be solved
+        for (int64_t j = 0; j < i; ++j) {
+            if (j >= known) {
+                // Wait until block j is solved.  Only the next block's
+                // workgroup is on the critical path; one that is d blocks
+                // further down has d block solves of slack and polls about
+                // every d * 0.4 us.  Every poll is an atomic on the one
+                // counter, so this keeps its cache line free for the critical
+                // reader.  The abort flag is looked at every 64 polls.
+                const int64_t dist = i - j - 1;
+                const int naps = (int)(dist < 16 ? dist : 16);
+                int64_t spins = 0;
+                for (;;) {
+                    int v = 0;
+                    if (lane == 0) v = flag_read(progress, zero);
+                    v = __builtin_amdgcn_readfirstlane(v);
+                    if (v > j) {
+                        known = v;
+                        break;
+                    }
+                    if ((++spins & 63) == 0) {
+                        int ab = 0;
+                        if (lane == 0) ab = flag_read(abort_flag, zero);
+                        ab = __builtin_amdgcn_readfirstlane(ab);
+                        if (ab != 0 || spins > spin_limit) {
+                            if (lane == 0) {
+                                flag_raise(abort_flag);
+                                s_abort = 1;
+                            }
+                            break;
                         }
                     }
-                    y[r] = x;
-#pragma unroll
-                    for (int q = r + 1; q < 16; ++q) y[q] = __builtin_fma(-Ls[b0 + q][b0 + r], x, y[q]);
+                    __builtin_amdgcn_s_sleep(1);
+                    for (int t = 0; t < naps; ++t) __builtin_amdgcn_s_sleep(16);
                 }
-                return ok;
-            };
-            if (!__all(step(std::true_type()))) step(std::false_type());
+            }
+            if (known > j) {
+                // -X_j into LDS: lane = row, up to 32 loads in flight at once
+                const int64_t gr = j * kTB + lane;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) Xs[b0 + r][lane] = y[r];
-#pragma unroll 1
-            for (int q = b0 + 16; q < kTB; ++q) {
-                double t = Xs[q][lane];
+                for (int k0 = 0; k0 < 16 * NCG; k0 += 32) {
+                    constexpr int kChunk = 16 * NCG < 32 ? 16 * NCG : 32;
+                    double xv[kChunk];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) t = __builtin_fma(-Ls[q][b0 + r], y[r], t);
-                Xs[q][lane] = t;
+                    for (int k = 0; k < kChunk; ++k)
+                        xv[k] = (k0 + k < ncols && gr < n) ? (double)coherent_load(bptr(gr, k0 + k)) : 0.0;
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) Xs[lane][k0 + k] = -xv[k];
+                }
+            }
+            __syncthreads();  // X_j staged, or the wait abandoned
+            if (s_abort != 0) {
+                aborted = true;
+                break;
+            }
+            __syncthreads();  // Xs is overwritten next
+        }
+    } else if (i > 0) {
+        // one update: the prefetch of L_{i,j+2} into `pre`, then
+        // acc += L_ij (-X_j) with L_ij from `cur`
+        auto update = [&](int64_t j, T(&cur)[16], T(&pre)[16]) -> bool {
+            load_a(j + 2 < i ? j + 2 : i - 1, pre);
+            __syncthreads();  // X_j staged, or the wait abandoned
+            if (s_abort != 0) return false;
+            // the B operands read from LDS four steps at a time, ahead of
+            // their products
+#pragma unroll
+            for (int k0 = 0; k0 < 16; k0 += 4) {
+                double xb[4][NCG];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int cg = 0; cg < NCG; ++cg) xb[ks][cg] = Xs[4 * (k0 + ks) + g][16 * cg + c];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int cg = 0; cg < NCG; ++cg)
+                        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)cur[k0 + ks], xb[ks][cg],
+                                                                      acc[cg], 0, 0, 0);
+            }
+            __syncthreads();  // Xs is overwritten next
+            return true;
+        };
+        load_a(0, ab0);
+        load_a(i > 1 ? 1 : 0, ab1);
+        for (int64_t j = 0; j < i; j += 3) {
+            if (!update(j, ab0, ab2) || (j + 1 < i && !update(j + 1, ab1, ab0)) ||
+                (j + 2 < i && !update(j + 2, ab2, ab1))) {
+                aborted = true;
+                break;
             }
         }
     }
-    __syncthreads();
+
+    // 3. The diagonal block: L_ii X_i = R_i as (D^-1 L_ii) X_i = D^-1 R_i, the
+    // right-hand sides divided by the diagonal first (correctly rounded), so
+    // each step of the substitution is a single fused multiply-add.
+    if (!UNIT && rows_wave) {
+#pragma unroll
+        for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * w + g + 4 * r;
+                acc[cg][r] = div_rn(acc[cg][r], Ds[row], Rs[row]);
+            }
+    }
+    if constexpr (ROWPAR) {
+        // wave w solves right-hand sides CPW w .. CPW w + CPW - 1, lane = row:
+        // after row r is final it is broadcast, and every row below subtracts
+        // its multiple (the rows at or above r multiply by the zero of
+        // D^-1 L_ii there)
+        if (rows_wave) {
+#pragma unroll
+            for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Xs[16 * w + g + 4 * r][16 * cg + c] = acc[cg][r];
+        }
+        __syncthreads();
+        if (rows_wave && CPW * w < ncols && !aborted) {
+            // this lane's row of -D^-1 L_ii in registers: the substitution
+            // then reads no memory
+            double lrow[kTB - 1];
+#pragma unroll
+            for (int r = 0; r < kTB - 1; ++r) lrow[r] = -Ls[lane][r];
+            double y[CPW];
+#pragma unroll
+            for (int k = 0; k < CPW; ++k) y[k] = Xs[lane][CPW * w + k];
+#pragma unroll
+            for (int r = 0; r < kTB - 1; ++r)
+#pragma unroll
+                for (int k = 0; k < CPW; ++k) y[k] = __builtin_fma(lrow[r], bcast_lane(y[k], r), y[k]);
+#pragma unroll
+            for (int k = 0; k < CPW; ++k) Xs[lane][CPW * w + k] = y[k];
+        }
+        __syncthreads();
+    } else {
+        // four 16-row steps: wave s hands its rows to LDS, wave 0 solves
+        // them by substitution in axpy order (lane = right-hand side), the
+        // row waves below subtract the product of their 16 x 16 block of
+        // D^-1 L_ii with the new unknowns on the matrix cores
+        const bool live = lane < ncols;
+#pragma unroll
+        for (int s = 0; s < kTB / 16; ++s) {
+            const int b0 = 16 * s;
+            if (w == s) {
+#pragma unroll
+                for (int cg = 0; cg < NCG; ++cg)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Xs[b0 + g + 4 * r][16 * cg + c] = acc[cg][r];
+            }
+            __syncthreads();
+            if (w == 0 && !aborted) {
+                double y[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) y[r] = live ? Xs[b0 + r][lane] : 0.0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+#pragma unroll
+                    for (int q = r + 1; q < 16; ++q) y[q] = __builtin_fma(-Ls[b0 + q][b0 + r], y[r], y[q]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) Xs[b0 + r][lane] = y[r];
+            }
+            __syncthreads();
+            if (rows_wave && w > s) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const double a = -Ls[16 * w + c][b0 + 4 * ks + g];
+#pragma unroll
+                    for (int cg = 0; cg < NCG; ++cg)
+                        acc[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            a, Xs[b0 + 4 * ks + g][16 * cg + c], acc[cg], 0, 0, 0);
+                }
+            }
+        }
+    }
     // X_i (NaN for an aborted block), stored along rows
-    for (int e = tid; e < kTB * 16 * NCG; e += 256) {
-        const int rr = e % kTB, col = e / kTB;
-        if (rr < rows && col < ncols)
-            *bptr(r0 + rr, col) = aborted ? (T)__builtin_nan("") : (T)Xs[rr][col];
+    if (rows_wave) {
+        const T nan = (T)__builtin_nan("");
+#pragma unroll
+        for (int k = 0; k < kXPer; ++k) {
+            const int e = tid + 256 * k, rr = e % kTB, col = e / kTB;
+            if (rr < rows && col < ncols)
+                coherent_store(bptr(r0 + rr, col), aborted ? nan : (T)Xs[rr][col]);
+        }
     }
-    __syncthreads();  // every store of the workgroup is complete
-    if (tid == 0) {
-        __threadfence();
-        flag_release(flags + i, 1);
-    }
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores are complete
+    __syncthreads();                // ... and every other thread's
+    if (tid == 0 && !aborted) flag_raise(progress);
 }
 
-template <typename T, bool UNIT, int NCG>
+template <typename T, bool UNIT, int NCG, int CPW>
 hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int ncols, int* flags,
                        hipStream_t s) {
-    const void* fn = (const void*)thin_kernel<T, UNIT, NCG>;
-    int per_cu = 0, cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess)
+    const void* fn = (const void*)thin_kernel<T, UNIT, NCG, CPW>;
+    // resident workgroups per CU, asked once per device (the first query
+    // costs more than a whole small solve)
+    static std::atomic<int> per_cu_of[kMaxDevices];
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return hipErrorInvalidValue;
+    int per_cu = per_cu_of[dev].load(std::memory_order_relaxed);
+    if (per_cu == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess)
+            return hipErrorInvalidValue;
+        per_cu_of[dev].store(per_cu, std::memory_order_relaxed);
+    }
     const int64_t nblk = (n + kTB - 1) / kTB;
     if (nblk > (int64_t)per_cu * cus) return hipErrorCooperativeLaunchTooLarge;
-    int64_t cnt = nblk + 1;
+    const int64_t cnt = thin_flag_count(n);
     hipLaunchKernelGGL(thin_flags_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                        flags, cnt);
     TriView l = L;
@@ -217,24 +401,27 @@ hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int ncols,
     int64_t nn = n, spin = (int64_t)1 << 22;
     int nc = ncols;
     int* fl = flags;
-    void* args[] = {&l, &b, &nn, &nc, &fl, &spin};
-    return hipLaunchCooperativeKernel(fn, dim3((unsigned)nblk), dim3(256), args, 0, s);
+    int zero = 0;
+    void* args[] = {&l, &b, &nn, &nc, &fl, &spin, &zero};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)nblk), dim3(kThreads), args, 0, s);
 }
 
 template <typename T, bool UNIT>
 hipError_t thin_by_groups(const TriView& L, const RhsView& B, int64_t n, int ncols, int* flags,
                           hipStream_t s) {
+    if (ncols <= 4) return thin_launch<T, UNIT, 1, 1>(L, B, n, ncols, flags, s);
+    if (ncols <= 8) return thin_launch<T, UNIT, 1, 2>(L, B, n, ncols, flags, s);
+    if (ncols <= 16) return thin_launch<T, UNIT, 1, 4>(L, B, n, ncols, flags, s);
     switch ((ncols + 15) / 16) {
-        case 1: return thin_launch<T, UNIT, 1>(L, B, n, ncols, flags, s);
-        case 2: return thin_launch<T, UNIT, 2>(L, B, n, ncols, flags, s);
-        case 3: return thin_launch<T, UNIT, 3>(L, B, n, ncols, flags, s);
-        default: return thin_launch<T, UNIT, 4>(L, B, n, ncols, flags, s);
+        case 2: return thin_launch<T, UNIT, 2, 0>(L, B, n, ncols, flags, s);
+        case 3: return thin_launch<T, UNIT, 3, 0>(L, B, n, ncols, flags, s);
+        default: return thin_launch<T, UNIT, 4, 0>(L, B, n, ncols, flags, s);
     }
 }
 
 }  // namespace
 
-int64_t thin_flag_count(int64_t n) { return (n + kTB - 1) / kTB + 1; }
+int64_t thin_flag_count(int64_t) { return kAbortAt + 1; }
 
 hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t ncols,
                        bool unit, int* flags, hipStream_t s) {

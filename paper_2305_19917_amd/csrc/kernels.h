@@ -92,8 +92,8 @@ hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* 
 
 // The whole canonical solve for at most 64 right-hand sides as one
 // persistent dataflow launch (cooperative: every 64-row block's workgroup
-// resident at once; blocks wait on readiness flags in `flags`, which must
-// hold thin_flag_count(n) ints of device memory).  Returns
+// resident at once; blocks wait on a counter of solved blocks in `flags`,
+// which must hold thin_flag_count(n) ints of device memory).  Returns
 // hipErrorCooperativeLaunchTooLarge, with nothing launched, when the device
 // cannot hold all blocks at once.
 int64_t thin_flag_count(int64_t n);

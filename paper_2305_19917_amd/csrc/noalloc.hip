@@ -1,9 +1,9 @@
 // Solve entry point for callers that cannot allocate device memory (code
 // under HIP graph capture, tight serving loops, harnesses that forbid
 // hipMalloc).  The only scratch memory of a native-precision solve is the
-// packed copy of its diagonal blocks; here it lives in a fixed file-scope
-// device array instead of the library's per-stream workspace, so a call
-// launches kernels and nothing else.
+// packed copy of its diagonal blocks, or the flags of the one-launch thin
+// solve; here it lives in a fixed file-scope device array instead of the
+// library's per-stream workspace, so a call launches kernels and nothing else.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -17,6 +17,7 @@ namespace redsea {
 namespace {
 
 constexpr size_t kScratchBytes = REDSEA_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kFlagBytes = 256;  // room for the thin solve's flags
 
 // Each device that loads the library holds its own copy of this array until
 // the process ends.  Host code never uses its name as an address: the device
@@ -76,13 +77,16 @@ int redsea_trsm_noalloc(int dtype, int side, int uplo, int trans, int diag, int6
     if (variant == 0) variant = VAR_RECURSIVE;
     const Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb);
     const int64_t leaf = pick_nb(nb, c.k);
-    if (alpha != 0.0 && packed_bytes(c, leaf) > kScratchBytes) return REDSEA_ERR_TOO_LARGE;
+    // the array: the thin solve's flags first, then the packed blocks
+    if ((size_t)thin_flag_count(c.k) * sizeof(int) > kFlagBytes ||
+        (alpha != 0.0 && kFlagBytes + packed_bytes(c, leaf) > kScratchBytes))
+        return REDSEA_ERR_TOO_LARGE;
     hipStream_t s = (hipStream_t)stream;
     if (alpha != 1.0) {
         if (launch_scale(dtype, B, m, n, ldb, alpha, s) != hipSuccess) return REDSEA_ERR_HIP;
         if (alpha == 0.0) return REDSEA_OK;
     }
-    return execute(c, variant, leaf, s, ptr);
+    return execute(c, variant, leaf, s, (unsigned char*)ptr + kFlagBytes, (int*)ptr);
 }
 
 }  // extern "C"

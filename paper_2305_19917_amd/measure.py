@@ -133,6 +133,30 @@ def row_thin():
         report("left lower N", nrhs, dL, ("L", "L", "N", "N"), 10)
 
 
+def row_thincross():
+    """The one-launch thin solve against the split recursive schedule (the
+    REDSEA_THIN switch) and the best iterative leaf, over orders and
+    right-hand-side counts up to the thin limit of 64."""
+    import os
+    import paper_2305_19917_amd as rs
+    import synth
+    for n in (512, 1024, 2048, 4096, 8192):
+        L = synth.dominant_lower(n, (1, 0, 0))
+        dL = rs.fortran_tensor(L)
+        for nrhs in (1, 4, 16, 32, 64):
+            B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+            dB0 = rs.fortran_tensor(B)
+            dB = dB0.t().clone().t()
+            out = {"row": "thincross", "n": n, "nrhs": nrhs}
+            for tag, env, variant, nb in (("thin_ms", "1", "recursive", 256), ("split_ms", "0", "recursive", 256),
+                                          ("iterative256_ms", "0", "iterative", 256)):
+                os.environ["REDSEA_THIN"] = env
+                out[tag] = round(_time(lambda: rs.trsm(dL, dB, variant=variant, nb=nb),
+                                       lambda: dB.copy_(dB0), 10), 4)
+            os.environ.pop("REDSEA_THIN", None)
+            _emit(out)
+
+
 # Constant-diagonal factors c of the kappa family at n = 16384 (matrix key
 # (2, 0, 0)) and the one-norm condition numbers they give, estimated with the
 # Hager-Higham estimator when the table of the family was made.
@@ -244,7 +268,8 @@ def row_batched():
         torch.cuda.empty_cache()
 
 
-ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "sides": row_sides,
+ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "thincross": row_thincross,
+        "sides": row_sides,
         "mixed": row_mixed,
         "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched}
 

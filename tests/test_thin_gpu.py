@@ -22,6 +22,13 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+@pytest.fixture(autouse=True)
+def _thin_on(monkeypatch):
+    # the kernel itself, for every count up to its limit of 64 (by default
+    # the library takes it only where it measured faster)
+    monkeypatch.setenv("REDSEA_THIN", "1")
+
+
 def _solve(A, B, side=0, uplo=0, trans=0, diag=0, alpha=1.0, dtype=np.float64, thin=True,
            monkeypatch=None):
     if monkeypatch is not None:
@@ -95,9 +102,25 @@ def test_thin_matches_split_schedule_within_rounding(monkeypatch):
     assert oracle.forward_error(X1, X0) <= 1e-12
 
 
-def test_more_blocks_than_resident_workgroups_fall_back():
-    # 20000 rows = 313 blocks of 64: more than one workgroup per CU can hold
-    # at once on 256 CUs, so the split schedule solves it
+@pytest.mark.parametrize("k,nrhs,thin", [(1000, 8, True), (1000, 16, True), (1000, 32, False),
+                                         (3000, 32, True), (3000, 33, False), (500, 64, False)])
+def test_default_takes_the_launch_where_it_pays(monkeypatch, k, nrhs, thin):
+    monkeypatch.delenv("REDSEA_THIN")
+    L = synth.dominant_lower(k, (57, k, 0))
+    B = synth.rhs_normal(k, nrhs, (57, nrhs, 1))
+    dA = rs.fortran_tensor(L)
+    dB = rs.fortran_tensor(B)
+    rs.trace_begin()
+    rs.trsm(dA, dB, variant="recursive", nb=256)
+    tr = rs.trace_end()
+    assert (tr["thin"][0] == 1) == thin and (tr["leaf"][0] > 0) == (not thin)
+    X = dB.cpu().numpy()
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
+
+
+def test_large_order():
+    # 20000 rows = 313 blocks of 64 (all resident at two workgroups per CU
+    # on 256 CUs; with fewer the split schedule solves it)
     k, nrhs = 20000, 3
     L = synth.dominant_lower(k, (56, 0, 0))
     B = synth.rhs_normal(k, nrhs, (56, 0, 1))

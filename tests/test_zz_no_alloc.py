@@ -67,11 +67,52 @@ def test_noalloc_rejects_oversize_and_refinement():
     assert L.redsea_trsm_noalloc(0, 0, 0, 0, 0, 100, 4, 1.0, 8, 100, 8, 100,
                                  ctypes.byref(opts), None) == 5
     # the largest FP64 order it takes at nb 256 (43 blocks) still solves
-    k, nrhs = 43 * 256, 16
+    # (40 right-hand sides: the split schedule with its packed blocks)
+    k, nrhs = 43 * 256, 40
     Lh = synth.dominant_lower(k, (26, 0, 0))
     B = synth.rhs_normal(k, nrhs, (26, 0, 1))
     X1, X2 = _both(Lh, B, variant="recursive", nb=256)
     assert np.array_equal(X1, X2)
+
+
+def test_noalloc_thin_big_then_small_and_captured():
+    # few right-hand sides: the one-launch solve, its flags in the array
+    for k, nrhs, key in [(3000, 8, (28, 0)), (700, 3, (28, 1)), (5000, 32, (28, 2))]:
+        _say("noalloc thin", k, nrhs)
+        L = synth.dominant_lower(k, key + (0,))
+        B = synth.rhs_normal(k, nrhs, key + (1,))
+        rs.trace_begin()
+        X1, X2 = _both(L, B, variant="recursive", nb=256)
+        assert rs.trace_end()["thin"][0] == 2
+        assert np.array_equal(X1, X2), k
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X2) <= 1e-14 * k
+    k, nrhs = 2500, 6
+    L = synth.dominant_lower(k, (28, 3, 0))
+    B = synth.rhs_normal(k, nrhs, (28, 3, 1))
+    dL, dB0 = rs.fortran_tensor(L), rs.fortran_tensor(B)
+    dB = dB0.clone()
+    ref = dB0.clone()
+    rs.trsm(dL, ref, variant="recursive", nb=256)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    rs.trsm_noalloc(dL, dB[:, :0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    _say("noalloc thin capture")
+    with torch.cuda.graph(g, stream=s):
+        rs.trsm_noalloc(dL, dB, variant="recursive", nb=256, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        X1, X2 = _both(synth.dominant_lower(900, (28, 4, 0)), synth.rhs_normal(900, 5, (28, 4, 1)),
+                       variant="recursive", nb=256)
+        assert np.array_equal(X1, X2)
+        dB.copy_(dB0)
+        torch.cuda.synchronize()
+        _say("noalloc thin replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(dB.cpu().numpy(), ref), rep
 
 
 def test_noalloc_graph_capture_and_replay():
