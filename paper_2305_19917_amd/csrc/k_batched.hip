@@ -59,94 +59,96 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
         if (t >= ntasks) break;  // uniform over the wave
         const BatchTask task = tasks[t];
         const BatchSys S = sys[task.sys];
-        const TS* A = (const TS*)S.a;
-        TS* B = (TS*)S.b;
         const int64_t k = S.k, c0 = task.c0;
         bool colok[W];
         int64_t bcol[W];
 #pragma unroll
         for (int G = 0; G < W; ++G) {
             colok[G] = c0 + 16 * G + c < S.nrhs;
-            bcol[G] = S.b_off + (c0 + 16 * G + (colok[G] ? c : 0)) * S.bc;
+            bcol[G] = S.b_off + (colok[G] ? c0 + 16 * G + c : c0) * S.bc;
         }
         const int nblk = (int)((k + 15) / 16);
-        // Operand reads.  FP64: predicated loads.  FP32: branch-free, an
-        // out-of-range lane reads a valid element (the first of the system or
-        // of the task's first column) and discards it; with a predicated load
-        // the widening to FP64 sits inside the branch and makes every load
-        // wait for its data before the next is issued.
-        const int64_t bsafe = S.b_off + c0 * S.bc;
-        auto bget = [&](int G, int64_t row) -> double {
-            const bool ok = colok[G] && row < k;
-            if constexpr (sizeof(TS) == 8) return ok ? (double)B[bcol[G] + row * S.br] : 0.0;
-            const TS v = B[ok ? bcol[G] + row * S.br : bsafe];
-            return ok ? (double)v : 0.0;
-        };
-        auto aget = [&](int64_t row, int64_t col) -> double {
-            const bool ok = row < k;
-            if constexpr (sizeof(TS) == 8) return ok ? (double)A[S.a_off + row * S.tr + col * S.tc] : 0.0;
-            const TS v = A[ok ? S.a_off + row * S.tr + col * S.tc : S.a_off];
-            return ok ? (double)v : 0.0;
+        // Operand reads are unconditional, through global-address-space
+        // pointers, with clamped indices: a read past the order or past the
+        // task's columns fetches a valid element (row k - 1, the task's first
+        // column) that only feeds accumulator rows or columns that are never
+        // stored.  Every value stays untouched until its use (the sign of L
+        // is the MFMA's A negation, alpha is applied after the products), so
+        // a step's loads are in flight together and the ring of D operand
+        // sets is D deep.  (A predicated or post-processed load makes the
+        // compiler wait for it right where it is issued.)
+        typedef const __attribute__((address_space(1))) TS* GConst;
+        typedef __attribute__((address_space(1))) TS* GMut;
+        const GConst Ag = (GConst)S.a;
+        const GConst Bg = (GConst)S.b;
+        const GMut Bw = (GMut)S.b;
+        auto bidx = [&](int G, int64_t row) -> int64_t { return bcol[G] + (row < k ? row : k - 1) * S.br; };
+        auto aidx = [&](int64_t row, int64_t col) -> int64_t {
+            return S.a_off + (row < k ? row : k - 1) * S.tr + (col < k ? col : k - 1) * S.tc;
         };
         int bad = 0;
         for (int p = 0; p < nblk; ++p) {
             v4d acc[W];
+            TS bv[W][4];  // alpha B_p, applied after the products
+            TS dv[4];     // this lane's entries of the diagonal block: rows g + 4r, column c
 #pragma unroll
-            for (int G = 0; G < W; ++G)
+            for (int G = 0; G < W; ++G) {
+                acc[G] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc[G][r] = alpha != 0.0 ? alpha * bget(G, 16 * p + g + 4 * r) : 0.0;  // BLAS: B := 0
-            if (alpha != 0.0) {
+                for (int r = 0; r < 4; ++r) bv[G][r] = Bg[bidx(G, 16 * p + g + 4 * r)];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dv[r] = Ag[aidx(16 * p + g + 4 * r, 16 * p + c)];
+            if (alpha != 0.0) {  // BLAS: alpha = 0 gives B := 0
+                // acc -= L_pq X_q, q < p, on the matrix cores; operand set d of
+                // the ring holds step q = q0 + d and is reloaded for step
+                // q + D right after its MFMAs (past the last step it reloads
+                // step p - 1, unused); each block of L feeds the W groups
+                TS xa[D][W][4], aa[D][4];
+                auto load_set = [&](int d, int q) {
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+                        for (int G = 0; G < W; ++G) xa[d][G][kk] = Bg[bidx(G, 16 * q + 4 * kk + g)];
+                        aa[d][kk] = Ag[aidx(16 * p + c, 16 * q + 4 * kk + g)];
+                    }
+                };
+                if (p > 0) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) load_set(d, d < p ? d : p - 1);
+                    for (int q0 = 0; q0 < p; q0 += D) {
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            const int q = q0 + d;
+                            if (q < p) {  // uniform over the wave
+#pragma unroll
+                                for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                    for (int G = 0; G < W; ++G)
+                                        acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                            (double)aa[d][kk], (double)xa[d][G][kk], acc[G], 0, 0,
+                                            1 /* negate A */);
+                            }
+                            load_set(d, q + D < p ? q + D : p - 1);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int G = 0; G < W; ++G)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[G][r] = __builtin_fma(alpha, (double)bv[G][r], acc[G][r]);
                 // diagonal block (identity past the order) and the reciprocals
-                // of its diagonal; independent of the products below
+                // of its diagonal
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = g + 4 * r;  // row of the block, column c
-                    const int64_t gi = 16 * p + i, gj = 16 * p + c;
+                    const int64_t gi = 16 * p + i;
                     double v = 0.0;
                     if (gi >= k) v = (i == c) ? 1.0 : 0.0;
-                    else if (i == c) v = UNIT ? 1.0 : aget(gi, gj);
-                    else if (i > c) v = aget(gi, gj);
+                    else if (i == c) v = UNIT ? 1.0 : (double)dv[r];
+                    else if (i > c) v = (double)dv[r];
                     Ls[w][c * 16 + i] = v;
                     if (!UNIT && i == c) Rs[w][c] = 1.0 / v;
-                }
-                // acc -= L_pq X_q, q < p, on the matrix cores; the operands
-                // of step q + D are requested right after step q's MFMAs have
-                // used their registers (a ring of D operand sets), so D - 1
-                // steps of loads are in flight while one multiplies; each
-                // block of L feeds the W column groups
-                double xa[D][W][4], aa[D][4];
-#pragma unroll
-                for (int d = 0; d < D; ++d)
-                    if (d < p) {
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-                            for (int G = 0; G < W; ++G) xa[d][G][kk] = bget(G, 16 * d + 4 * kk + g);
-                            aa[d][kk] = -aget(16 * p + c, 16 * d + 4 * kk + g);
-                        }
-                    }
-                for (int q0 = 0; q0 < p; q0 += D) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const int q = q0 + d;
-                        if (q >= p) break;  // uniform over the wave
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                            for (int G = 0; G < W; ++G)
-                                acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(aa[d][kk], xa[d][G][kk],
-                                                                             acc[G], 0, 0, 0);
-                        if (q + D < p) {
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) {
-#pragma unroll
-                                for (int G = 0; G < W; ++G)
-                                    xa[d][G][kk] = bget(G, 16 * (q + D) + 4 * kk + g);
-                                aa[d][kk] = -aget(16 * p + c, 16 * (q + D) + 4 * kk + g);
-                            }
-                        }
-                    }
                 }
                 // the columns' rows of the block
 #pragma unroll
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                     const int64_t row = 16 * p + g + 4 * r;
                     if (colok[G] && row < k) {
                         const TS v = (TS)acc[G][r];
-                        B[bcol[G] + row * S.br] = v;
+                        Bw[bcol[G] + row * S.br] = v;
                         if (!__builtin_isfinite((double)v)) bad = 1;
                     }
                 }

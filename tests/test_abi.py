@@ -105,7 +105,8 @@ def test_picker_outside_trained_shapes_takes_default_schedule():
     L = rs.lib()
     conf = ctypes.c_int(7)
     var, nb, prec = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    for dtype, n, nrhs, want_nb in [(0, 16384, 16384, 256), (1, 8192, 8192, 256),
+    # the stored network was trained on orders 65 .. 32445 and widths 1 .. 16238
+    for dtype, n, nrhs, want_nb in [(0, 65536, 1024, 256), (1, 4096, 65536, 256),
                                     (0, 100, 100000, 128), (0, 32, 4, 128)]:
         c = L.redsea_pick(dtype, n, nrhs, 0.0, ctypes.byref(conf))
         assert conf.value == 0
