@@ -268,10 +268,29 @@ def row_batched():
         torch.cuda.empty_cache()
 
 
+def row_batchedfp64(tile=1, runs=5):
+    """The FP64 batch of the batched row at one task shape, plain launches
+    only (no graph, no tuning): the command the counter runs profile."""
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    ns, ks = synth.batch_shapes(2000, (3, 0, 2))
+    As = [rs.fortran_tensor(synth.dominant_lower(int(n), (3, i, 0))) for i, n in enumerate(ns)]
+    Bs = [rs.fortran_tensor(synth.rhs_normal(int(n), int(k), (3, i, 1))) for i, (n, k) in enumerate(zip(ns, ks))]
+    info = torch.zeros(len(Bs), dtype=torch.int32, device="cuda")
+    plan = rs.BatchPlan(As, Bs, tile=tile)
+    ms = _time(lambda: plan.run(info), lambda: None, runs)
+    byts = float(sum(8 * (n * (n + 1) / 2 + 2.0 * n * k) for n, k in zip(ns, ks)))
+    _emit({"row": "batchedfp64", "tile": tile, "runs": runs + 1, "ms": round(ms, 4),
+           "algorithmic_bytes": byts, "info_nonzero": int((info != 0).sum().item())})
+    plan.close()
+
+
 ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "thincross": row_thincross,
         "sides": row_sides,
         "mixed": row_mixed,
-        "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched}
+        "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched,
+        "batchedfp64": row_batchedfp64}
 
 
 def main(argv):
