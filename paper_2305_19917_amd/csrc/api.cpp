@@ -454,18 +454,19 @@ size_t packed_bytes(const Canon& c, int64_t nb) {
 // REDSEA_THIN=0 never.
 constexpr int64_t kThinMaxRhs = 64;
 
-bool thin_pays(int64_t n, int64_t nrhs) { return nrhs <= 16 || (nrhs <= 32 && n >= 2048); }
+bool thin_pays(int64_t n, int64_t nrhs) {
+    return nrhs <= kThinMaxRhs && (nrhs <= 16 || (nrhs <= 32 && n >= 2048));
+}
 
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed,
             int* thin_flags) {
-    if (variant == VAR_RECURSIVE && (!packed || thin_flags) && !c.gemm_bf16 &&
-        c.nrhs <= kThinMaxRhs) {
+    if (variant == VAR_RECURSIVE && (!packed || thin_flags) && !c.gemm_bf16) {
         const char* env = std::getenv("REDSEA_THIN");
         const int mode = env ? std::atoi(env) : -1;  // -1: by the measured crossover
         if (mode == 1 || (mode != 0 && thin_pays(c.k, c.nrhs))) {
             WsLease fl;
             if (!packed) {
-                int rc = workspace(6, (size_t)thin_flag_count(c.k) * sizeof(int), s, fl);
+                int rc = workspace(6, (size_t)thin_flag_count(c.k, c.nrhs) * sizeof(int), s, fl);
                 if (rc) return rc;
                 thin_flags = (int*)fl.ptr;
             }
@@ -474,7 +475,7 @@ int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed
             });
             if (e == hipSuccess) return REDSEA_OK;
             if (e != hipErrorCooperativeLaunchTooLarge) return REDSEA_ERR_HIP;
-            (void)hipGetLastError();  // more blocks than resident workgroups: the split below
+            (void)hipGetLastError();  // a device that cannot hold one workgroup: the split below
         }
     }
     const int64_t kleaf = leaf_rows(nb);

@@ -35,7 +35,10 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTB = 64;     // rows per block
 constexpr int kTCols = 64;  // right-hand sides at most
-constexpr int kAbortAt = 32;  // flags index of the abort flag (128 bytes on)
+// flags: [0] the task queue, [kAbortAt] abort, [kGroupFlags + 32 g] the
+// solved-block counter of column group g (each in a cache line of its own)
+constexpr int kAbortAt = 32;
+constexpr int kGroupFlags = 64;
 constexpr int kMaxDevices = 64;
 constexpr int kStager = 4;             // the wave that waits for and stages solved blocks
 constexpr int kThreads = 64 * (kStager + 1);
@@ -96,9 +99,9 @@ __device__ __forceinline__ double div_rn(double a, double d, double r) {
 // blocks and stages them in LDS.  CPW > 0: the diagonal block's substitution
 // runs with its rows across the lanes, CPW right-hand sides per wave;
 // CPW = 0: in 16-row steps with one lane per right-hand side.
-template <typename T, bool UNIT, int NCG, int CPW>
+template <typename T, bool UNIT, int NCG, int CPW, bool PERSIST>
 __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B, int64_t n,
-                                                           int ncols, int* flags,
+                                                           int64_t nrhs, int ngroups, int* flags,
                                                            int64_t spin_limit, int zero) {
     constexpr int kXPer = kTB * 16 * NCG / 256;  // elements of a row block per row thread
     constexpr bool ROWPAR = CPW > 0;
@@ -111,18 +114,48 @@ __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B,
     // the wave index as a wave-uniform value: every branch on it is a scalar
     // branch, so a wave runs only its own role's code (no exec-masked pass
     // through the other's barriers and memory waits)
-    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, c = lane & 15;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid0 = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid0 >> 6);
     const bool rows_wave = w < kStager;  // waves 0-3
-    const int64_t i = blockIdx.x;
-    const int64_t r0 = i * kTB;
-    const int rows = (int)(n - r0 < kTB ? n - r0 : kTB);
-    int* progress = flags;
+    __shared__ int s_task;
+    int* queue = flags;
     int* abort_flag = flags + kAbortAt;
+    const int64_t nblk = (n + kTB - 1) / kTB;
+    const int64_t ntasks = nblk * ngroups;
     auto tget = [&](int64_t r, int64_t col) -> double {
         return (double)A[L.off + r * L.tr + col * L.tc];
     };
-    auto bptr = [&](int64_t r, int64_t col) -> T* { return Bp + B.off + r * B.br + col * B.bc; };
+    // Tasks (row block i, column group grp) are claimed in the order
+    // t = i * ngroups + grp.  A task depends only on earlier row blocks of its
+    // own group, which were claimed before it by resident workgroups, so the
+    // earliest unfinished task can always proceed.
+    // PERSIST: a grid of the resident workgroups loops over the queue;
+    // otherwise every task has a workgroup of its own (t = blockIdx.x, the
+    // same order) and the body runs once
+  for (int64_t pass = 0;; ++pass) {
+    int64_t t;
+    if constexpr (PERSIST) {
+        if (tid0 == 0) s_task = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        t = s_task;
+        __syncthreads();  // s_task is read before it is claimed again
+    } else {
+        t = pass == 0 ? (int64_t)blockIdx.x : ntasks;
+    }
+    if (t >= ntasks) break;  // uniform over the workgroup
+    // the lane indexes as an opaque value per task: the address arithmetic
+    // derived from them is recomputed in each pass instead of being hoisted
+    // out of the loop and held in registers for the whole launch
+    int tidv = tid0;
+    asm volatile("" : "+v"(tidv));
+    const int tid = tidv, lane = tid & 63, g = lane >> 4, c = lane & 15;
+    const int64_t i = t / ngroups, grp = t % ngroups;
+    const int64_t r0 = i * kTB;
+    const int rows = (int)(n - r0 < kTB ? n - r0 : kTB);
+    const int ncols = (int)(nrhs - grp * kTCols < kTCols ? nrhs - grp * kTCols : kTCols);
+    const int64_t boff = B.off + grp * kTCols * B.bc;
+    int* progress = flags + kGroupFlags + 32 * grp;  // solved blocks of this group
+    auto bptr = [&](int64_t r, int64_t col) -> T* { return Bp + boff + r * B.br + col * B.bc; };
 
     // 1. Work that waits for nothing, done while earlier blocks are solved.
     // This wave's 16 rows of the block, in the accumulator layout (lane l,
@@ -372,12 +405,17 @@ __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B,
     __builtin_amdgcn_s_waitcnt(0);  // this thread's stores are complete
     __syncthreads();                // ... and every other thread's
     if (tid == 0 && !aborted) flag_raise(progress);
+  }
 }
 
 template <typename T, bool UNIT, int NCG, int CPW>
-hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int ncols, int* flags,
+hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int64_t nrhs, int* flags,
                        hipStream_t s) {
-    const void* fn = (const void*)thin_kernel<T, UNIT, NCG, CPW>;
+    const int64_t nblk = (n + kTB - 1) / kTB;
+    const int ngroups = (int)((nrhs + kTCols - 1) / kTCols);
+    const int64_t ntasks = nblk * ngroups;
+    const void* fn1 = (const void*)thin_kernel<T, UNIT, NCG, CPW, false>;
+    const void* fnp = (const void*)thin_kernel<T, UNIT, NCG, CPW, true>;
     // resident workgroups per CU, asked once per device (the first query
     // costs more than a whole small solve)
     static std::atomic<int> per_cu_of[kMaxDevices];
@@ -387,51 +425,55 @@ hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int ncols,
         return hipErrorInvalidValue;
     int per_cu = per_cu_of[dev].load(std::memory_order_relaxed);
     if (per_cu == 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fnp, kThreads, 0) != hipSuccess)
             return hipErrorInvalidValue;
         per_cu_of[dev].store(per_cu, std::memory_order_relaxed);
     }
-    const int64_t nblk = (n + kTB - 1) / kTB;
-    if (nblk > (int64_t)per_cu * cus) return hipErrorCooperativeLaunchTooLarge;
-    const int64_t cnt = thin_flag_count(n);
+    if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+    // every task a workgroup of its own when they all fit at once (one
+    // column group: the whole latency chain in flight), else a persistent
+    // grid of the resident workgroups working through the queue
+    const int64_t resident = (int64_t)per_cu * cus;
+    const int64_t grid = ntasks < resident ? ntasks : resident;
+    const int64_t cnt = thin_flag_count(n, nrhs);
     hipLaunchKernelGGL(thin_flags_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                        flags, cnt);
     TriView l = L;
     RhsView b = B;
-    int64_t nn = n, spin = (int64_t)1 << 22;
-    int nc = ncols;
+    int64_t nn = n, nr = nrhs, spin = (int64_t)1 << 22;
+    int ng = ngroups;
     int* fl = flags;
     int zero = 0;
-    void* args[] = {&l, &b, &nn, &nc, &fl, &spin, &zero};
-    return hipLaunchCooperativeKernel(fn, dim3((unsigned)nblk), dim3(kThreads), args, 0, s);
+    void* args[] = {&l, &b, &nn, &nr, &ng, &fl, &spin, &zero};
+    return hipLaunchCooperativeKernel(grid == ntasks ? fn1 : fnp, dim3((unsigned)grid), dim3(kThreads),
+                                      args, 0, s);
 }
 
 template <typename T, bool UNIT>
-hipError_t thin_by_groups(const TriView& L, const RhsView& B, int64_t n, int ncols, int* flags,
-                          hipStream_t s) {
-    if (ncols <= 4) return thin_launch<T, UNIT, 1, 1>(L, B, n, ncols, flags, s);
-    if (ncols <= 8) return thin_launch<T, UNIT, 1, 2>(L, B, n, ncols, flags, s);
-    if (ncols <= 16) return thin_launch<T, UNIT, 1, 4>(L, B, n, ncols, flags, s);
-    switch ((ncols + 15) / 16) {
-        case 2: return thin_launch<T, UNIT, 2, 0>(L, B, n, ncols, flags, s);
-        case 3: return thin_launch<T, UNIT, 3, 0>(L, B, n, ncols, flags, s);
-        default: return thin_launch<T, UNIT, 4, 0>(L, B, n, ncols, flags, s);
-    }
+hipError_t thin_by_width(const TriView& L, const RhsView& B, int64_t n, int64_t nrhs, int* flags,
+                         hipStream_t s) {
+    if (nrhs <= 4) return thin_launch<T, UNIT, 1, 1>(L, B, n, nrhs, flags, s);
+    if (nrhs <= 8) return thin_launch<T, UNIT, 1, 2>(L, B, n, nrhs, flags, s);
+    if (nrhs <= 16) return thin_launch<T, UNIT, 1, 4>(L, B, n, nrhs, flags, s);
+    if (nrhs <= 32) return thin_launch<T, UNIT, 2, 0>(L, B, n, nrhs, flags, s);
+    if (nrhs <= 48) return thin_launch<T, UNIT, 3, 0>(L, B, n, nrhs, flags, s);
+    return thin_launch<T, UNIT, 4, 0>(L, B, n, nrhs, flags, s);  // groups of 64
 }
 
 }  // namespace
 
-int64_t thin_flag_count(int64_t) { return kAbortAt + 1; }
+int64_t thin_flag_count(int64_t, int64_t nrhs) {
+    return kGroupFlags + 32 * ((nrhs + kTCols - 1) / kTCols);
+}
 
-hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t ncols,
+hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t nrhs,
                        bool unit, int* flags, hipStream_t s) {
-    if (n <= 0 || ncols <= 0) return hipSuccess;
-    if (ncols > kTCols) return hipErrorInvalidValue;
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
     if (dtype == 0)
-        return unit ? thin_by_groups<double, true>(L, B, n, (int)ncols, flags, s)
-                    : thin_by_groups<double, false>(L, B, n, (int)ncols, flags, s);
-    return unit ? thin_by_groups<float, true>(L, B, n, (int)ncols, flags, s)
-                : thin_by_groups<float, false>(L, B, n, (int)ncols, flags, s);
+        return unit ? thin_by_width<double, true>(L, B, n, nrhs, flags, s)
+                    : thin_by_width<double, false>(L, B, n, nrhs, flags, s);
+    return unit ? thin_by_width<float, true>(L, B, n, nrhs, flags, s)
+                : thin_by_width<float, false>(L, B, n, nrhs, flags, s);
 }
 
 }  // namespace redsea

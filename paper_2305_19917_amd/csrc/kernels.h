@@ -90,13 +90,12 @@ hipError_t launch_scale(int dtype, void* b, int64_t m, int64_t n, int64_t ldb, d
 hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* out,
                                 hipStream_t s);
 
-// The whole canonical solve for at most 64 right-hand sides as one
-// persistent dataflow launch (cooperative: every 64-row block's workgroup
-// resident at once; blocks wait on a counter of solved blocks in `flags`,
-// which must hold thin_flag_count(n) ints of device memory).  Returns
-// hipErrorCooperativeLaunchTooLarge, with nothing launched, when the device
-// cannot hold all blocks at once.
-int64_t thin_flag_count(int64_t n);
+// The whole canonical solve as one persistent dataflow launch over tasks
+// (64-row block, group of up to 64 right-hand sides), cooperative so that
+// every workgroup is resident; blocks wait on per-group counters of solved
+// blocks in `flags`, which must hold thin_flag_count(n, nrhs) ints of device
+// memory.
+int64_t thin_flag_count(int64_t n, int64_t nrhs);
 hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t ncols,
                        bool unit, int* flags, hipStream_t s);
 

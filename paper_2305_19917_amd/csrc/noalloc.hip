@@ -17,7 +17,7 @@ namespace redsea {
 namespace {
 
 constexpr size_t kScratchBytes = REDSEA_NOALLOC_SCRATCH_BYTES;
-constexpr size_t kFlagBytes = 256;  // room for the thin solve's flags
+constexpr size_t kFlagBytes = (size_t)64 << 10;  // the one-launch solve's flags (up to ~32000 right-hand sides)
 
 // Each device that loads the library holds its own copy of this array until
 // the process ends.  Host code never uses its name as an address: the device
@@ -77,16 +77,16 @@ int redsea_trsm_noalloc(int dtype, int side, int uplo, int trans, int diag, int6
     if (variant == 0) variant = VAR_RECURSIVE;
     const Canon c = canonicalize(dtype, side, uplo, trans, diag, m, n, A, lda, B, ldb);
     const int64_t leaf = pick_nb(nb, c.k);
-    // the array: the thin solve's flags first, then the packed blocks
-    if ((size_t)thin_flag_count(c.k) * sizeof(int) > kFlagBytes ||
-        (alpha != 0.0 && kFlagBytes + packed_bytes(c, leaf) > kScratchBytes))
+    // the array: the one-launch solve's flags first, then the packed blocks
+    if (alpha != 0.0 && kFlagBytes + packed_bytes(c, leaf) > kScratchBytes)
         return REDSEA_ERR_TOO_LARGE;
+    int* flags = (size_t)thin_flag_count(c.k, c.nrhs) * sizeof(int) <= kFlagBytes ? (int*)ptr : nullptr;
     hipStream_t s = (hipStream_t)stream;
     if (alpha != 1.0) {
         if (launch_scale(dtype, B, m, n, ldb, alpha, s) != hipSuccess) return REDSEA_ERR_HIP;
         if (alpha == 0.0) return REDSEA_OK;
     }
-    return execute(c, variant, leaf, s, (unsigned char*)ptr + kFlagBytes, (int*)ptr);
+    return execute(c, variant, leaf, s, (unsigned char*)ptr + kFlagBytes, flags);
 }
 
 }  // extern "C"

@@ -157,6 +157,31 @@ def row_thincross():
             _emit(out)
 
 
+def row_widecross():
+    """The one-launch solve over column groups against the split recursive
+    and the iterative schedules, from 64 right-hand sides up."""
+    import os
+    import paper_2305_19917_amd as rs
+    import synth
+    for n in (2048, 4096, 8192):
+        L = synth.dominant_lower(n, (1, 0, 0))
+        dL = rs.fortran_tensor(L)
+        for nrhs in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+            B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+            dB0 = rs.fortran_tensor(B)
+            dB = dB0.t().clone().t()
+            out = {"row": "widecross", "n": n, "nrhs": nrhs}
+            for tag, env, variant in (("thin_ms", "1", "recursive"), ("split_ms", "0", "recursive"),
+                                      ("iterative256_ms", "0", "iterative")):
+                os.environ["REDSEA_THIN"] = env
+                out[tag] = round(_time(lambda: rs.trsm(dL, dB, variant=variant, nb=256),
+                                       lambda: dB.copy_(dB0), 5), 4)
+            os.environ.pop("REDSEA_THIN", None)
+            out["thin_tflops"] = round(float(n) * n * nrhs / (out["thin_ms"] * 1e-3) / 1e12, 2)
+            _emit(out)
+            del dB, dB0
+
+
 # Constant-diagonal factors c of the kappa family at n = 16384 (matrix key
 # (2, 0, 0)) and the one-norm condition numbers they give, estimated with the
 # Hager-Higham estimator when the table of the family was made.
@@ -287,6 +312,7 @@ def row_batchedfp64(tile=1, runs=5):
 
 
 ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "thincross": row_thincross,
+        "widecross": row_widecross,
         "sides": row_sides,
         "mixed": row_mixed,
         "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched,

@@ -120,9 +120,56 @@ def test_default_takes_the_launch_where_it_pays(monkeypatch, k, nrhs, thin):
 
 def test_large_order():
     # 20000 rows = 313 blocks of 64 (all resident at two workgroups per CU
-    # on 256 CUs; with fewer the split schedule solves it)
+    # on 256 CUs; with fewer, a persistent grid works through them)
     k, nrhs = 20000, 3
     L = synth.dominant_lower(k, (56, 0, 0))
     B = synth.rhs_normal(k, nrhs, (56, 0, 1))
     X = _solve(L, B)
     assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * k
+
+
+# Wider B: the same launch over tasks (64-row block, group of 64 right-hand
+# sides), persistent when the tasks outnumber the resident workgroups.
+@pytest.mark.parametrize("k,nrhs", [(1, 65), (100, 100), (777, 129), (2000, 300), (3000, 1000)])
+def test_wide_backward_error(k, nrhs):
+    L = synth.dominant_lower(k, (58, k, 0))
+    B = synth.rhs_normal(k, nrhs, (58, nrhs, 1))
+    X = _solve(L, B)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 1e-14 * max(k, 1)
+    assert oracle.forward_error(X, oracle.trsm_plain(0, 0, 0, 0, 1.0, L, B)) <= 1e-11
+
+
+@pytest.mark.parametrize("side,uplo,trans,diag", FLAGS)
+def test_wide_all_flags(side, uplo, trans, diag):
+    k, nrhs = 500, 150
+    L = synth.unit_lower(k, (59, k, 0)) if diag else synth.dominant_lower(k, (59, k, 0))
+    A = np.array(L if uplo == 0 else L.T, order="F")
+    A[np.triu_indices(k, 1) if uplo == 0 else np.tril_indices(k, -1)] = np.nan
+    B = synth.rhs_normal(*((k, nrhs) if side == 0 else (nrhs, k)), key=(59, k, 1))
+    X = _solve(A, B, side, uplo, trans, diag, alpha=2.0)
+    assert oracle.backward_error(side, uplo, trans, diag, 2.0, A, B, X) <= 1e-14 * k
+
+
+def test_wide_fp32_and_exact():
+    k, nrhs = 1200, 200
+    L = synth.dominant_lower(k, (60, 0, 0)).astype(np.float32).astype(np.float64)
+    B = synth.rhs_normal(k, nrhs, (60, 0, 1)).astype(np.float32).astype(np.float64)
+    X = _solve(L, B, dtype=np.float32)
+    assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, X) <= 5e-6 * k
+    for side, uplo, trans, diag in [(0, 0, 0, 0), (1, 1, 1, 1)]:
+        m, n = (300, 170) if side == 0 else (170, 300)
+        A, Bi, Xt = synth.integer_exact(m, n, (61, side, uplo), side, uplo, trans, diag)
+        assert np.array_equal(_solve(A, Bi, side, uplo, trans, diag), Xt)
+
+
+def test_wide_persistent_queue_order_8192():
+    # 128 row blocks x 16 groups = 2048 tasks on the resident workgroups
+    n, nrhs = 8192, 1024
+    L = synth.dominant_lower(n, (1, 0, 0))
+    B = synth.rhs_normal(n, nrhs, (1, 0, 1))
+    X = _solve(L, B)
+    cols = np.arange(0, nrhs, 97)
+    eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, B[:, cols], X[:, cols])
+    _say("wide n=8192 nrhs=1024 eta %.2e" % eta)
+    assert eta <= 1e-14 * n
+    assert np.array_equal(X, _solve(L, B))  # run to run, whatever the claim order
