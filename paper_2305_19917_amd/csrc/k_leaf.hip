@@ -3,9 +3,14 @@
 // The leaf is the "TS" task that the paper's models leave at the finest
 // granularity (Sec. V-A: the white triangles of the recursive model; the
 // same tasks appear in Sec. V-B and V-C).  Here it runs on the GPU, by the
-// forward substitution of Sec. IV in axpy order (after unknown k is divided
-// out, every later row is updated with it), on a packed canonical copy of the
-// diagonal block.  Leaves of up to 128 rows keep the block's whole triangle
+// forward substitution of Sec. IV in axpy order (every later row is updated
+// with each new unknown), on a packed canonical copy of the diagonal block
+// scaled by rows: the packed block holds D^-1 L (each strictly lower entry
+// divided by its row's diagonal, correctly rounded; the diagonal itself
+// kept), and the leaf divides its panel by the diagonal once before the
+// substitution, so no division sits on the chain of dependent steps.  This
+// is substitution on the row-scaled system (componentwise backward stable;
+// a diagonal system is still one correctly rounded division per entry).  Leaves of up to 128 rows keep the block's whole triangle
 // in LDS (leaf_mfma_kernel); 256-row leaves keep only its 16 x 16 diagonal
 // blocks there and apply the rest as matrix-core products between two waves
 // (leaf_ilv_kernel).  FP32 data is solved by the same kernels: it is widened
@@ -35,7 +40,9 @@ __global__ __launch_bounds__(256) void pack_diag_kernel(const T* __restrict__ A,
         if (r < c) v = T(0);
         else if (gi >= m) v = (r == c) ? T(1) : T(0);
         else if (r == c && unit) v = T(1);
-        else v = A[off + gi * tr + gj * tc];
+        else if (r == c || unit) v = A[off + gi * tr + gj * tc];
+        else  // row-scaled: L(r, c) / L(r, r), correctly rounded
+            v = (T)((double)A[off + gi * tr + gj * tc] / (double)A[off + gi * tr + gi * tc]);
         P[blk * stride + idx] = v;
     }
 }
@@ -75,11 +82,10 @@ __device__ __forceinline__ void wave_sync() {
 // Step 1-2 of a 16-row diagonal block, for one wave's 16 columns: `frag`
 // holds rows g + 4r of the block (column c) in accumulator layout; the block
 // is gathered through the wave's LDS buffer Xw so that every lane holds its
-// column's 16 values, solved by substitution against the 16 x 16 lower
-// triangle Lb (LDS, element (row j, column i) at Lb[i*16 + j], axpy order,
-// one IEEE division per row unless UNIT), and each lane keeps its own four
-// rows of the solution in `frag`.
-template <bool UNIT>
+// column's 16 values, solved by substitution against the unit lower 16 x 16
+// triangle Lb (LDS, element (row j, column i) at Lb[i*16 + j], axpy order;
+// the diagonal entries are not read), and each lane keeps its own four rows
+// of the solution in `frag`.
 __device__ __forceinline__ void solve_diag16(const double* Lb, double (*Xw)[17], v4d& frag, int g,
                                              int c) {
 #pragma unroll
@@ -89,7 +95,7 @@ __device__ __forceinline__ void solve_diag16(const double* Lb, double (*Xw)[17],
 #pragma unroll
     for (int i = 0; i < 16; ++i) y[i] = Xw[i][c];
     // Column i+1 of the block is read from LDS while column i is applied, so
-    // the chain of a step is one division and one fused multiply-add.
+    // the chain of a step is one fused multiply-add.
     double cur[16], nxt[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) cur[j] = Lb[j];
@@ -99,9 +105,7 @@ __device__ __forceinline__ void solve_diag16(const double* Lb, double (*Xw)[17],
 #pragma unroll
             for (int j = i + 1; j < 16; ++j) nxt[j] = Lb[(i + 1) * 16 + j];
         }
-        double x = y[i];
-        if (!UNIT) x = x / cur[i];
-        y[i] = x;
+        const double x = y[i];
 #pragma unroll
         for (int j = i + 1; j < 16; ++j) y[j] = __builtin_fma(-cur[j], x, y[j]);
 #pragma unroll
@@ -128,7 +132,8 @@ __device__ __forceinline__ void solve_diag16(const double* Lb, double (*Xw)[17],
 // solved by 16-row diagonal blocks:
 //   1. the 16 x 16 block of each column is gathered into one lane (every
 //      lane of the column's four lane groups gets the whole column, through
-//      LDS) and solved there by substitution, one IEEE division per row;
+//      LDS) and solved there by unit-diagonal substitution (the panel was
+//      divided by the diagonal beforehand);
 //   2. each lane keeps its own four rows of the result;
 //   3. every later 16-row fragment is updated on the matrix cores,
 //      frag_p -= L_ps X_s, whose B operand for k-slice kk is exactly register
@@ -169,10 +174,18 @@ __global__ __launch_bounds__(256) void leaf_mfma_kernel(const TS* __restrict__ P
             fr[f][r] = (colok && (FULL || row < rows)) ? (double)bp[row * br] : 0.0;
         }
     __syncthreads();
+    if (!UNIT) {
+        // the panel divided by the diagonal (correctly rounded) once: the
+        // packed block holds D^-1 L, so every step below is unit-diagonal
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fr[f][r] = fr[f][r] / Ls[f * 256 + (g + 4 * r) * 17];
+    }
 #pragma unroll
     for (int s = 0; s < NF; ++s) {
-        // 1-2. solve the diagonal block; each lane keeps its rows
-        solve_diag16<UNIT>(Ls + s * 256, Xs[w], fr[s], g, c);
+        // 1-2. solve the (unit) diagonal block; each lane keeps its rows
+        solve_diag16(Ls + s * 256, Xs[w], fr[s], g, c);
         // 3. matrix-core update of the fragments below; A operand for
         // k-slice kk: element (16p + c, 16s + 4kk + g) of the triangle
 #pragma unroll
@@ -265,6 +278,14 @@ __global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict
         for (int k = 0; k < NBK * 256 / NT; ++k) Ds[tid + k * NT] = t[k];
     }
     __syncthreads();
+    if (!UNIT) {
+        // the panel divided by the diagonal (correctly rounded) once: the
+        // packed block holds D^-1 L, so every step below is unit-diagonal
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fr[j][r] = fr[j][r] / Ds[(2 * j + v) * 256 + (g + 4 * r) * 17];
+    }
     // A operands of block (p, s), k-slices 0..3, from the fragment-ordered
     // copy behind the square (one 32- or 16-byte load per lane)
     const TS* F = P + NP2 * NP2;
@@ -307,7 +328,7 @@ __global__ __launch_bounds__(128 * CG) void leaf_ilv_kernel(const TS* __restrict
         const int par = s & 1, jo = s >> 1;  // owner parity, owner's fragment
         const bool own = v == par;
         if (own) {
-            solve_diag16<UNIT>(Ds + s * 256, Xs[cg], fr[jo], g, c);
+            solve_diag16(Ds + s * 256, Xs[cg], fr[jo], g, c);
             Xb[par][cg][lane] = fr[jo];
         }
         __syncthreads();  // x_s published
