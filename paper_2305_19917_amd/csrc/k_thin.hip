@@ -1,24 +1,26 @@
-// Thin right-hand sides (up to 64): the whole forward substitution as one
-// persistent dataflow launch.
+// Thin right-hand sides: the whole forward substitution as one dataflow
+// launch.
 //
 // With few right-hand sides the split of Sec. IV leaves the GPU idle: every
 // leaf is a serial chain on a handful of CUs and every update a small
-// product, each a separate launch on the critical path.  Here row block i
-// (64 rows) belongs to workgroup i of a cooperative launch (all workgroups
-// resident at once).  The workgroup starts from its rows of B and, for j = 0,
-// 1, ..., i - 1, waits until block j is solved (a readiness flag in global
-// memory, device-coherent accesses), stages X_j in LDS and
-// subtracts L_ij X_j on the matrix cores (v_mfma_f64_16x16x4f64, one 16-row
-// slice of the block per wave).  Then it solves its 64 x 64 diagonal block by
-// substitution in axpy order, one lane per right-hand side, each unknown the
-// correctly rounded quotient (fdiv.h), stores X_i and raises its flag.  The
-// products of a block with the blocks solved long before run while the
-// blocks just before it are still being solved, so the critical path is the
-// chain of diagonal solves plus one product per block.
+// product, each a separate launch on the critical path.  Here a task (row
+// block i of 64 rows, group of up to 64 right-hand sides) belongs to one
+// workgroup of a cooperative launch (all workgroups resident at once).  It
+// starts from its rows of B and, for j = 0, 1, ..., i - 1, waits until block
+// j of its group is solved (a counter of solved blocks in global memory, read
+// and raised with agent-scope atomics), stages X_j in LDS and subtracts
+// L_ij X_j on the matrix cores (v_mfma_f64_16x16x4f64, one 16-row slice of
+// the block per wave).  Then it solves its 64 x 64 diagonal block in
+// row-scaled form (the block and its right-hand sides divided by the
+// diagonal, correctly rounded; unit-diagonal substitution after), stores X_i
+// and raises the counter.  The products of a block with the blocks solved
+// long before run while the blocks just before it are still being solved,
+// so the critical path is the chain of diagonal solves plus one product per
+// block.  When the tasks outnumber the resident workgroups, a persistent
+// grid takes them from a queue in dependency order.
 //
-// Waits are bounded: a workgroup that waits longer than its limit (which only
-// happens when the device cannot run all workgroups at once) raises a global
-// abort flag, writes NaN for its block and publishes it; every other waiting
+// Waits are bounded: a workgroup that waits longer than its limit raises a
+// global abort flag and writes NaN for its block; every other waiting
 // workgroup sees the abort flag and does the same, so the launch always ends.
 #include <hip/hip_runtime.h>
 
