@@ -31,7 +31,8 @@ struct redsea_batch_plan {
     int device = 0;
     redsea::BatchSys* d_sys = nullptr;
     redsea::BatchTask* d_tasks = nullptr;
-    int* d_counter = nullptr;
+    redsea::BatchQueues queues{};
+    int* d_counter = nullptr;  // kBatchCounterInts ints
     // systems above the panel limit, solved by the single-system path
     std::vector<redsea::Canon> big;
     std::vector<int64_t> big_index;
@@ -206,19 +207,43 @@ int redsea_batched_plan_create(int dtype, int side, int uplo, int trans, int dia
         redsea_batched_plan_destroy(P);
         return REDSEA_ERR_ALLOC;
     }
+    // One queue per XCD: systems go to the queues longest-first, each to the
+    // least loaded so far (their tiles stay together); each queue is then
+    // ordered longest task first.
+    std::vector<double> sys_work(sys.size(), 0.0);
+    for (auto& w : work) sys_work[(size_t)w.second.sys] += w.first;
+    std::vector<int32_t> order;
+    for (size_t i = 0; i < sys_work.size(); ++i)
+        if (sys_work[i] > 0.0) order.push_back((int32_t)i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return sys_work[(size_t)x] > sys_work[(size_t)y]; });
+    std::vector<int> queue_of(sys.size(), 0);
+    double load[kBatchQueues] = {};
+    for (int32_t i : order) {
+        int q = 0;
+        for (int u = 1; u < kBatchQueues; ++u)
+            if (load[u] < load[q]) q = u;
+        queue_of[(size_t)i] = q;
+        load[q] += sys_work[(size_t)i];
+    }
     std::stable_sort(work.begin(), work.end(),
                      [](const std::pair<double, BatchTask>& x, const std::pair<double, BatchTask>& y) {
                          return x.first > y.first;
                      });
     std::vector<BatchTask> tasks;
     tasks.reserve(work.size());
-    for (auto& w : work) tasks.push_back(w.second);
+    for (int q = 0; q < kBatchQueues; ++q) {
+        P->queues.start[q] = (int)tasks.size();
+        for (auto& w : work)
+            if (queue_of[(size_t)w.second.sys] == q) tasks.push_back(w.second);
+        P->queues.count[q] = (int)tasks.size() - P->queues.start[q];
+    }
     P->ntasks = (int)tasks.size();
     if (sys.empty()) sys.resize(1);
     bool ok = hipMalloc(&P->d_sys, sys.size() * sizeof(BatchSys)) == hipSuccess &&
               hipMalloc(&P->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(BatchTask)) ==
                   hipSuccess &&
-              hipMalloc(&P->d_counter, sizeof(int)) == hipSuccess;
+              hipMalloc(&P->d_counter, kBatchCounterInts * sizeof(int)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         redsea_batched_plan_destroy(P);
@@ -250,7 +275,7 @@ int redsea_batched_plan_run(redsea_batch_plan* P, int* info, void* stream) {
     if (P->ntasks > 0 &&
         launch_batched(P->dtype, P->unit, kBatchTileGroups[P->tile - 1],
                        kBatchTileDepth[P->tile - 1], P->d_sys, P->d_tasks,
-                       P->ntasks, P->d_counter, info, P->alpha, P->grid, s) != hipSuccess)
+                       P->queues, P->d_counter, info, P->alpha, P->grid, s) != hipSuccess)
         return REDSEA_ERR_HIP;
     for (size_t i = 0; i < P->big.size(); ++i) {
         const Canon& c = P->big[i];

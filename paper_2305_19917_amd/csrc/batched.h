@@ -24,14 +24,27 @@ struct BatchTask {
 
 constexpr int64_t kBatchMaxOrder = 1024;  // panel of 16 columns in LDS
 
-hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_t s);
+// Task queues, one per XCD: the tasks of a system all sit in one queue, so
+// the column tiles of a system run on one XCD and share its triangle in that
+// XCD's L2.  A workgroup claims from the queue of its XCD (workgroups are
+// dispatched to the XCDs round-robin) and then from the others in turn, so
+// every task is claimed exactly once wherever it runs.  Counters are 32 ints
+// apart (one cache line each).
+constexpr int kBatchQueues = 8;
+constexpr int kBatchCounterInts = 32 * kBatchQueues;
+struct BatchQueues {
+    int start[kBatchQueues];  // first task of each queue in the task array
+    int count[kBatchQueues];
+};
+
+hipError_t launch_batch_reset(int* counters, int* info, int64_t count, hipStream_t s);
 // groups: column groups of 16 per task (1 or 2; with 2 a wave solves 32
 // right-hand sides and each block of the triangle it loads feeds both).
 // depth: steps of the left-looking product whose operands are in flight (1,
 // 2 or 4).  Neither changes the arithmetic: results are bitwise the same.
 hipError_t launch_batched(int dtype, bool unit, int groups, int depth, const BatchSys* sys,
-                          const BatchTask* tasks, int ntasks, int* counter, int* info,
-                          double alpha, int grid, hipStream_t s);
+                          const BatchTask* tasks, const BatchQueues& queues, int* counters,
+                          int* info, double alpha, int grid, hipStream_t s);
 
 // Task shapes the batched solver can run (index = tile option - 1):
 // {column groups per task, operand prefetch depth, workgroups of four waves

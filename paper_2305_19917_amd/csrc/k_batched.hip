@@ -2,9 +2,11 @@
 // order and right-hand-side count in one launch (the solve of Sec. IV per
 // system; spec batching pattern).
 //
-// Work is a list of tasks (system, tile of up to 16 right-hand sides), sorted
-// longest-first on the host.  Every wave repeatedly claims the next task from
-// a counter and solves it alone, left-looking over 16-row blocks with its
+// Work is a list of tasks (system, tile of up to 16 right-hand sides) in one
+// queue per XCD (a system's tiles in one queue, each queue longest-first).
+// Every wave repeatedly claims the next task, from its own XCD's queue first
+// (the tiles of a system then share its triangle in that XCD's L2), and
+// solves it alone, left-looking over 16-row blocks with its
 // 16 x 16 block of the right-hand sides held in the v_mfma_f64_16x16x4f64
 // accumulator layout (lane l, register r = row l/16 + 4r, column l % 16):
 //   acc = alpha B_p;  acc -= L_pq X_q for every solved block q < p on the
@@ -33,17 +35,17 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void batch_reset_kernel(int* counter, int* info, int64_t count) {
+__global__ void batch_reset_kernel(int* counters, int* info, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         info[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kBatchCounterInts) counters[threadIdx.x] = 0;
 }
 
 template <typename TS, bool UNIT, int W, int D>
 __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict__ sys,
                                                       const BatchTask* __restrict__ tasks,
-                                                      int ntasks, int* __restrict__ counter,
+                                                      BatchQueues queues, int* __restrict__ counters,
                                                       int* __restrict__ info, double alpha) {
     __shared__ double Xs[4][W][16][17];  // per-wave gather buffer, one per column group
     __shared__ double Ls[4][16 * 16];    // per-wave diagonal block, (j, i) at [i*16 + j]
@@ -52,12 +54,18 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
     // the group whose column c this lane solves in the substitution (the four
     // row slices g of a column split evenly over the W groups)
     const int sg = W == 1 ? 0 : (g >> 1);
+    const int home = (int)(blockIdx.x % kBatchQueues);  // this workgroup's XCD
+    int visited = 0;                                     // queues found empty
     for (;;) {
+        const int q = (home + visited) % kBatchQueues;
         int t = 0;
-        if (lane == 0) t = atomicAdd(counter, 1);
+        if (lane == 0) t = atomicAdd(counters + 32 * q, 1);
         t = __shfl(t, 0);
-        if (t >= ntasks) break;  // uniform over the wave
-        const BatchTask task = tasks[t];
+        if (t >= queues.count[q]) {  // uniform over the wave
+            if (++visited == kBatchQueues) break;
+            continue;
+        }
+        const BatchTask task = tasks[queues.start[q] + t];
         const BatchSys S = sys[task.sys];
         const int64_t k = S.k, c0 = task.c0;
         bool colok[W];
@@ -249,42 +257,43 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
 
 }  // namespace
 
-hipError_t launch_batch_reset(int* counter, int* info, int64_t count, hipStream_t s) {
+hipError_t launch_batch_reset(int* counters, int* info, int64_t count, hipStream_t s) {
     int64_t blocks = (count + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counter, info,
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counters, info,
                        count);
     return hipGetLastError();
 }
 
 template <int W, int D>
 void launch_batched_wd(int dtype, bool unit, const BatchSys* sys, const BatchTask* tasks,
-                       int ntasks, int* counter, int* info, double alpha, int grid, hipStream_t s) {
+                       const BatchQueues& qs, int* counters, int* info, double alpha, int grid,
+                       hipStream_t s) {
     if (dtype == 0) {
         if (unit)
             hipLaunchKernelGGL((batched_kernel<double, true, W, D>), dim3(grid), dim3(256), 0, s,
-                               sys, tasks, ntasks, counter, info, alpha);
+                               sys, tasks, qs, counters, info, alpha);
         else
             hipLaunchKernelGGL((batched_kernel<double, false, W, D>), dim3(grid), dim3(256), 0, s,
-                               sys, tasks, ntasks, counter, info, alpha);
+                               sys, tasks, qs, counters, info, alpha);
     } else {
         if (unit)
             hipLaunchKernelGGL((batched_kernel<float, true, W, D>), dim3(grid), dim3(256), 0, s,
-                               sys, tasks, ntasks, counter, info, alpha);
+                               sys, tasks, qs, counters, info, alpha);
         else
             hipLaunchKernelGGL((batched_kernel<float, false, W, D>), dim3(grid), dim3(256), 0, s,
-                               sys, tasks, ntasks, counter, info, alpha);
+                               sys, tasks, qs, counters, info, alpha);
     }
 }
 
 hipError_t launch_batched(int dtype, bool unit, int groups, int depth, const BatchSys* sys,
-                          const BatchTask* tasks, int ntasks, int* counter, int* info,
-                          double alpha, int grid, hipStream_t s) {
-#define REDSEA_BATCHED_CASE(W, D)                                                            \
-    if (groups == W && depth == D) {                                                         \
-        launch_batched_wd<W, D>(dtype, unit, sys, tasks, ntasks, counter, info, alpha, grid, s); \
-        return hipGetLastError();                                                            \
+                          const BatchTask* tasks, const BatchQueues& queues, int* counters,
+                          int* info, double alpha, int grid, hipStream_t s) {
+#define REDSEA_BATCHED_CASE(W, D)                                                              \
+    if (groups == W && depth == D) {                                                           \
+        launch_batched_wd<W, D>(dtype, unit, sys, tasks, queues, counters, info, alpha, grid, s); \
+        return hipGetLastError();                                                              \
     }
     REDSEA_BATCHED_CASE(1, 1)
     REDSEA_BATCHED_CASE(1, 2)
