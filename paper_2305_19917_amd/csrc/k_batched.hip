@@ -47,6 +47,13 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                                                       const BatchTask* __restrict__ tasks,
                                                       BatchQueues queues, int* __restrict__ counters,
                                                       int* __restrict__ info, double alpha) {
+    // The first QL solved blocks of a wave's task stay in LDS, in B-operand
+    // order (k-slice kk of block q: XL[w][q][G][kk][lane] = X_q(4 kk + g, c),
+    // which is register kk of the solved accumulator fragment), so the
+    // left-looking products read them on chip instead of from memory (56 or
+    // 48 KB per workgroup: two workgroups still fit per CU).
+    constexpr int QL = 7 / W;
+    __shared__ double XL[4][QL][W][4][64];
     __shared__ double Xs[4][W][16][17];  // per-wave gather buffer, one per column group
     __shared__ double Ls[4][16 * 16];    // per-wave diagonal block, (j, i) at [i*16 + j]
     __shared__ double Rs[4][16];         // per-wave 1 / diagonal
@@ -122,22 +129,57 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                     }
                 };
                 if (p > 0) {
+                    // (a) the solved blocks kept in LDS: only L is loaded
+                    const int pl = p < QL ? p : QL;
+                    {
+                        TS al[D][4];
+                        auto load_l = [&](int d, int q) {
 #pragma unroll
-                    for (int d = 0; d < D; ++d) load_set(d, d < p ? d : p - 1);
-                    for (int q0 = 0; q0 < p; q0 += D) {
+                            for (int kk = 0; kk < 4; ++kk) al[d][kk] = Ag[aidx(16 * p + c, 16 * q + 4 * kk + g)];
+                        };
 #pragma unroll
-                        for (int d = 0; d < D; ++d) {
-                            const int q = q0 + d;
-                            if (q < p) {  // uniform over the wave
+                        for (int d = 0; d < D; ++d) load_l(d, d < pl ? d : pl - 1);
+                        for (int q0 = 0; q0 < pl; q0 += D) {
 #pragma unroll
-                                for (int kk = 0; kk < 4; ++kk)
+                            for (int d = 0; d < D; ++d) {
+                                const int q = q0 + d;
+                                if (q < pl) {  // uniform over the wave
+                                    double xl[4][W];
 #pragma unroll
-                                    for (int G = 0; G < W; ++G)
-                                        acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                            (double)aa[d][kk], (double)xa[d][G][kk], acc[G], 0, 0,
-                                            1 /* negate A */);
+                                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                        for (int G = 0; G < W; ++G) xl[kk][G] = XL[w][q][G][kk][lane];
+#pragma unroll
+                                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                        for (int G = 0; G < W; ++G)
+                                            acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                (double)al[d][kk], xl[kk][G], acc[G], 0, 0,
+                                                1 /* negate A */);
+                                }
+                                load_l(d, q + D < pl ? q + D : pl - 1);
                             }
-                            load_set(d, q + D < p ? q + D : p - 1);
+                        }
+                    }
+                    // (b) the rest, X from memory through the ring
+                    if (p > pl) {
+#pragma unroll
+                        for (int d = 0; d < D; ++d) load_set(d, pl + d < p ? pl + d : p - 1);
+                        for (int q0 = pl; q0 < p; q0 += D) {
+#pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                const int q = q0 + d;
+                                if (q < p) {  // uniform over the wave
+#pragma unroll
+                                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                                        for (int G = 0; G < W; ++G)
+                                            acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                (double)aa[d][kk], (double)xa[d][G][kk], acc[G], 0, 0,
+                                                1 /* negate A */);
+                                }
+                                load_set(d, q + D < p ? q + D : p - 1);
+                            }
                         }
                     }
                 }
@@ -236,6 +278,14 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchSys* __restrict
                         for (int r = 0; r < 4; ++r) acc[G][r] = Xs[w][G][g + 4 * r][c];
                 }
                 wave_sync();  // Xs and Ls are reused by the next block
+            }
+            if (p < QL) {
+                // the solved block for the later products, as stored (rounded
+                // to the system's type: the same bits a read from memory gives)
+#pragma unroll
+                for (int G = 0; G < W; ++G)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) XL[w][p][G][kk][lane] = (double)(TS)acc[G][kk];
             }
 #pragma unroll
             for (int G = 0; G < W; ++G)
