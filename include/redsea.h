@@ -113,9 +113,10 @@ enum {
  *
  * Follows the three-stage split of Sec. IV applied recursively, iteratively
  * or in blocked rounds (Sec. V) as selected by opts.  A recursive solve with
- * few right-hand sides (at most 16, or 32 from order 2048 on, where it was
- * measured faster) runs instead as one cooperative dataflow launch over
- * 64-row blocks; the environment variable REDSEA_THIN=1 / 0 takes it for
+ * at most 256 right-hand sides (where it was measured faster than every
+ * split schedule) runs instead as one cooperative dataflow launch over
+ * 64-row blocks and groups of 16 right-hand sides, and AUTO solves of such
+ * widths take it; the environment variable REDSEA_THIN=1 / 0 takes it for
  * every width / never.  dtype gives the element
  * type of A and B (double or float).  Argument numbers for the -i return:
  * dtype 1, side 2, uplo 3, trans 4, diag 5, m 6, n 7, alpha 8, A 9, lda 10,

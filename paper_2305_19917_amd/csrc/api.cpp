@@ -444,26 +444,28 @@ size_t packed_bytes(const Canon& c, int64_t nb) {
 }
 
 // Recursive solves with few right-hand sides run as one dataflow launch
-// (k_thin.hip) when the library owns the memory.  Measured on MI355X (FP64,
-// diagonally dominant lower triangle), the launch beats both the split
-// recursive and the iterative schedules for at most 16 right-hand sides at
-// every order from 512 to 8192 (n = 8192, one right-hand side: 0.47 ms
-// against 1.58 ms iterative and 2.59 ms split) and for at most 32 from
-// n = 2048 on; with 64 the split schedules are as fast or faster.
-// REDSEA_THIN=1 takes the launch for any count up to its limit of 64,
-// REDSEA_THIN=0 never.
-constexpr int64_t kThinMaxRhs = 64;
+// (k_thin.hip; groups of 16 right-hand sides solved side by side) when the
+// library owns the memory.  Measured on MI355X (FP64, diagonally dominant
+// lower triangle), the launch beats both the split recursive and the
+// iterative schedules (nb 256) up to 256 right-hand sides at every order
+// from 512 to 8192 (n = 8192: 0.47 / 0.77 / 1.22 ms for 1 / 64 / 256 right-
+// hand sides against 1.47 / 1.66 / 1.82 ms iterative), and loses from 512 on.
+// REDSEA_THIN=1 takes the launch for every width, REDSEA_THIN=0 never.
+constexpr int64_t kThinMaxRhs = 256;
 
-bool thin_pays(int64_t n, int64_t nrhs) {
-    return nrhs <= kThinMaxRhs && (nrhs <= 16 || (nrhs <= 32 && n >= 2048));
+bool thin_pays(int64_t, int64_t nrhs) { return nrhs <= kThinMaxRhs; }
+
+// Whether a recursive solve of this shape takes the one-launch solve.
+bool thin_taken(int64_t n, int64_t nrhs) {
+    const char* env = std::getenv("REDSEA_THIN");
+    const int mode = env ? std::atoi(env) : -1;  // -1: by the measured crossover
+    return mode == 1 || (mode != 0 && thin_pays(n, nrhs));
 }
 
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed,
             int* thin_flags) {
     if (variant == VAR_RECURSIVE && (!packed || thin_flags) && !c.gemm_bf16) {
-        const char* env = std::getenv("REDSEA_THIN");
-        const int mode = env ? std::atoi(env) : -1;  // -1: by the measured crossover
-        if (mode == 1 || (mode != 0 && thin_pays(c.k, c.nrhs))) {
+        if (thin_taken(c.k, c.nrhs)) {
             WsLease fl;
             if (!packed) {
                 int rc = workspace(6, (size_t)thin_flag_count(c.k, c.nrhs) * sizeof(int), s, fl);
@@ -682,14 +684,24 @@ int redsea_trsm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
         // not confident); a condition estimate, when not given, is taken as
         // that of a diagonally dominant matrix of this order
         const int64_t k = side == REDSEA_LEFT ? m : n, nrhs = side == REDSEA_LEFT ? n : m;
-        double kap = chosen.kappa;
-        if (!(kap > 0.0) && (rc = diag_kappa(dtype, side, uplo, trans, diag, m, n, A, lda, s, &kap)))
-            return rc;
         int confident = 0;
-        int cand = pick_candidate(dtype, k, nrhs, kap, &confident);
-        if (!confident) {
-            int tuned = tuned_candidate(dtype, k, nrhs, kap, s);
-            if (tuned >= 0) cand = tuned;
+        int cand = -1;
+        if (thin_taken(k, nrhs)) {
+            // the one-launch solve, measured faster than every split schedule
+            // at these widths (the picker's timings of the recursive
+            // candidates there predate it)
+            variant = VAR_RECURSIVE;
+            precision = REDSEA_PREC_NATIVE;
+        } else {
+            double kap = chosen.kappa;
+            if (!(kap > 0.0) &&
+                (rc = diag_kappa(dtype, side, uplo, trans, diag, m, n, A, lda, s, &kap)))
+                return rc;
+            cand = pick_candidate(dtype, k, nrhs, kap, &confident);
+            if (!confident) {
+                int tuned = tuned_candidate(dtype, k, nrhs, kap, s);
+                if (tuned >= 0) cand = tuned;
+            }
         }
         if (cand >= 0) decode_candidate(cand, &variant, &nb, &precision);
         chosen.variant = variant;

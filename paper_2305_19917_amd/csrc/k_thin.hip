@@ -36,7 +36,13 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTB = 64;     // rows per block
-constexpr int kTCols = 64;  // right-hand sides at most
+constexpr int kTCols = 64;  // right-hand sides per task at most
+// Right-hand sides per group: up to 64, groups of 16 on the row-parallel
+// solve (the groups of one launch are independent solves that each read the
+// triangle; at these widths that costs less than the slower 16-row-step
+// solve of a wider group), wider B in groups of 64.
+constexpr int64_t kThinRowParMax = 256;  // groups of 16 up to this width
+inline int64_t thin_group_width(int64_t nrhs) { return nrhs <= kThinRowParMax ? 16 : kTCols; }
 // flags: [0] the task queue, [kAbortAt] abort, [kGroupFlags + 32 g] the
 // solved-block counter of column group g (each in a cache line of its own)
 constexpr int kAbortAt = 32;
@@ -103,7 +109,7 @@ __device__ __forceinline__ double div_rn(double a, double d, double r) {
 // CPW = 0: in 16-row steps with one lane per right-hand side.
 template <typename T, bool UNIT, int NCG, int CPW, bool PERSIST>
 __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B, int64_t n,
-                                                           int64_t nrhs, int ngroups, int* flags,
+                                                           int64_t nrhs, int ngroups, int gw, int* flags,
                                                            int64_t spin_limit, int zero) {
     constexpr int kXPer = kTB * 16 * NCG / 256;  // elements of a row block per row thread
     constexpr bool ROWPAR = CPW > 0;
@@ -154,8 +160,8 @@ __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B,
     const int64_t i = t / ngroups, grp = t % ngroups;
     const int64_t r0 = i * kTB;
     const int rows = (int)(n - r0 < kTB ? n - r0 : kTB);
-    const int ncols = (int)(nrhs - grp * kTCols < kTCols ? nrhs - grp * kTCols : kTCols);
-    const int64_t boff = B.off + grp * kTCols * B.bc;
+    const int ncols = (int)(nrhs - grp * gw < gw ? nrhs - grp * gw : gw);
+    const int64_t boff = B.off + grp * gw * B.bc;
     int* progress = flags + kGroupFlags + 32 * grp;  // solved blocks of this group
     auto bptr = [&](int64_t r, int64_t col) -> T* { return Bp + boff + r * B.br + col * B.bc; };
 
@@ -414,7 +420,8 @@ template <typename T, bool UNIT, int NCG, int CPW>
 hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int64_t nrhs, int* flags,
                        hipStream_t s) {
     const int64_t nblk = (n + kTB - 1) / kTB;
-    const int ngroups = (int)((nrhs + kTCols - 1) / kTCols);
+    const int64_t gw = thin_group_width(nrhs);
+    const int ngroups = (int)((nrhs + gw - 1) / gw);
     const int64_t ntasks = nblk * ngroups;
     const void* fn1 = (const void*)thin_kernel<T, UNIT, NCG, CPW, false>;
     const void* fnp = (const void*)thin_kernel<T, UNIT, NCG, CPW, true>;
@@ -443,10 +450,10 @@ hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int64_t nr
     TriView l = L;
     RhsView b = B;
     int64_t nn = n, nr = nrhs, spin = (int64_t)1 << 22;
-    int ng = ngroups;
+    int ng = ngroups, gwi = (int)gw;
     int* fl = flags;
     int zero = 0;
-    void* args[] = {&l, &b, &nn, &nr, &ng, &fl, &spin, &zero};
+    void* args[] = {&l, &b, &nn, &nr, &ng, &gwi, &fl, &spin, &zero};
     return hipLaunchCooperativeKernel(grid == ntasks ? fn1 : fnp, dim3((unsigned)grid), dim3(kThreads),
                                       args, 0, s);
 }
@@ -456,16 +463,15 @@ hipError_t thin_by_width(const TriView& L, const RhsView& B, int64_t n, int64_t 
                          hipStream_t s) {
     if (nrhs <= 4) return thin_launch<T, UNIT, 1, 1>(L, B, n, nrhs, flags, s);
     if (nrhs <= 8) return thin_launch<T, UNIT, 1, 2>(L, B, n, nrhs, flags, s);
-    if (nrhs <= 16) return thin_launch<T, UNIT, 1, 4>(L, B, n, nrhs, flags, s);
-    if (nrhs <= 32) return thin_launch<T, UNIT, 2, 0>(L, B, n, nrhs, flags, s);
-    if (nrhs <= 48) return thin_launch<T, UNIT, 3, 0>(L, B, n, nrhs, flags, s);
+    if (nrhs <= kThinRowParMax) return thin_launch<T, UNIT, 1, 4>(L, B, n, nrhs, flags, s);
     return thin_launch<T, UNIT, 4, 0>(L, B, n, nrhs, flags, s);  // groups of 64
 }
 
 }  // namespace
 
 int64_t thin_flag_count(int64_t, int64_t nrhs) {
-    return kGroupFlags + 32 * ((nrhs + kTCols - 1) / kTCols);
+    const int64_t gw = thin_group_width(nrhs);
+    return kGroupFlags + 32 * ((nrhs + gw - 1) / gw);
 }
 
 hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t nrhs,

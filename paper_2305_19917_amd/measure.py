@@ -163,10 +163,10 @@ def row_widecross():
     import os
     import paper_2305_19917_amd as rs
     import synth
-    for n in (2048, 4096, 8192):
+    for n in (512, 2048, 4096, 8192):
         L = synth.dominant_lower(n, (1, 0, 0))
         dL = rs.fortran_tensor(L)
-        for nrhs in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        for nrhs in (64, 96, 128, 192, 256, 512, 1024):
             B = synth.rhs_normal(n, nrhs, (1, 0, 1))
             dB0 = rs.fortran_tensor(B)
             dB = dB0.t().clone().t()

@@ -102,8 +102,8 @@ def test_thin_matches_split_schedule_within_rounding(monkeypatch):
     assert oracle.forward_error(X1, X0) <= 1e-12
 
 
-@pytest.mark.parametrize("k,nrhs,thin", [(1000, 8, True), (1000, 16, True), (1000, 32, False),
-                                         (3000, 32, True), (3000, 33, False), (500, 64, False)])
+@pytest.mark.parametrize("k,nrhs,thin", [(1000, 8, True), (1000, 32, True), (500, 64, True),
+                                         (3000, 256, True), (3000, 257, False), (500, 300, False)])
 def test_default_takes_the_launch_where_it_pays(monkeypatch, k, nrhs, thin):
     monkeypatch.delenv("REDSEA_THIN")
     L = synth.dominant_lower(k, (57, k, 0))
@@ -173,3 +173,19 @@ def test_wide_persistent_queue_order_8192():
     _say("wide n=8192 nrhs=1024 eta %.2e" % eta)
     assert eta <= 1e-14 * n
     assert np.array_equal(X, _solve(L, B))  # run to run, whatever the claim order
+
+
+def test_auto_takes_the_launch_where_it_pays(monkeypatch):
+    # AUTO solves (no variant, nb or precision given) go straight to the
+    # one-launch solve at these widths, without the picker or its estimate
+    monkeypatch.delenv("REDSEA_THIN")
+    for k, nrhs, thin in [(2000, 100, True), (2000, 300, False)]:
+        L = synth.dominant_lower(k, (62, k, 0))
+        B = synth.rhs_normal(k, nrhs, (62, nrhs, 1))
+        dA = rs.fortran_tensor(L)
+        dB = rs.fortran_tensor(B)
+        rs.trace_begin()
+        rs.trsm(dA, dB)
+        tr = rs.trace_end()
+        assert (tr["thin"][0] == 1) == thin, (k, nrhs)
+        assert oracle.backward_error(0, 0, 0, 0, 1.0, L, B, dB.cpu().numpy()) <= 1e-14 * k

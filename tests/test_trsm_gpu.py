@@ -343,6 +343,7 @@ def test_lookahead_changes_no_bit(k, nrhs, nb, dtype, monkeypatch):
     sequential order."""
     L = synth.dominant_lower(k, (24, k, 0))
     B = synth.rhs_normal(k, nrhs, (24, k, 1))
+    monkeypatch.setenv("REDSEA_THIN", "0")  # the split schedules, whatever the width
     for variant in ("recursive", "iterative"):
         monkeypatch.setenv("REDSEA_LOOKAHEAD", "0")
         X0 = gpu_solve(L, B, variant=variant, nb=nb, dtype=dtype)

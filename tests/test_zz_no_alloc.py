@@ -67,8 +67,8 @@ def test_noalloc_rejects_oversize_and_refinement():
     assert L.redsea_trsm_noalloc(0, 0, 0, 0, 0, 100, 4, 1.0, 8, 100, 8, 100,
                                  ctypes.byref(opts), None) == 5
     # the largest FP64 order it takes at nb 256 (43 blocks) still solves
-    # (40 right-hand sides: the split schedule with its packed blocks)
-    k, nrhs = 43 * 256, 40
+    # (300 right-hand sides: the split schedule with its packed blocks)
+    k, nrhs = 43 * 256, 300
     Lh = synth.dominant_lower(k, (26, 0, 0))
     B = synth.rhs_normal(k, nrhs, (26, 0, 1))
     X1, X2 = _both(Lh, B, variant="recursive", nb=256)
