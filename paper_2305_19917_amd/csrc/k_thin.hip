@@ -37,10 +37,10 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kTB = 64;     // rows per block
 constexpr int kTCols = 64;  // right-hand sides per task at most
-// Right-hand sides per group: up to 64, groups of 16 on the row-parallel
-// solve (the groups of one launch are independent solves that each read the
-// triangle; at these widths that costs less than the slower 16-row-step
-// solve of a wider group), wider B in groups of 64.
+// Right-hand sides per group: up to 256 right-hand sides, groups of 16 on
+// the row-parallel solve (the groups of one launch are independent solves
+// that each read the triangle; at these widths that costs less than the
+// slower 16-row-step solve of a wider group); wider B in groups of 64.
 constexpr int64_t kThinRowParMax = 256;  // groups of 16 up to this width
 inline int64_t thin_group_width(int64_t nrhs) { return nrhs <= kThinRowParMax ? 16 : kTCols; }
 // flags: [0] the task queue, [kAbortAt] abort, [kGroupFlags + 32 g] the
@@ -101,12 +101,13 @@ __device__ __forceinline__ double div_rn(double a, double d, double r) {
     return q;
 }
 
-// flags[0]: the number of solved blocks (blocks finish in order, each
-// needing its predecessor); flags[kAbortAt]: abort, in a cache line of its
-// own.  Waves 0-3 own the block's rows; wave 4 (kStager) waits for solved
-// blocks and stages them in LDS.  CPW > 0: the diagonal block's substitution
-// runs with its rows across the lanes, CPW right-hand sides per wave;
-// CPW = 0: in 16-row steps with one lane per right-hand side.
+// One task: a 64-row block of one group of gw right-hand sides (flags as
+// laid out above; the blocks of a group finish in order, each needing its
+// predecessor, so one counter per group says how many are solved).  Waves
+// 0-3 own the block's rows; wave 4 (kStager) waits for solved blocks and
+// stages them in LDS.  CPW > 0: the diagonal block's substitution runs with
+// its rows across the lanes, CPW right-hand sides per wave; CPW = 0: in
+// 16-row steps with one lane per right-hand side.
 template <typename T, bool UNIT, int NCG, int CPW, bool PERSIST>
 __global__ __launch_bounds__(kThreads, 1) void thin_kernel(TriView L, RhsView B, int64_t n,
                                                            int64_t nrhs, int ngroups, int gw, int* flags,
@@ -447,6 +448,8 @@ hipError_t thin_launch(const TriView& L, const RhsView& B, int64_t n, int64_t nr
     const int64_t cnt = thin_flag_count(n, nrhs);
     hipLaunchKernelGGL(thin_flags_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                        flags, cnt);
+    const hipError_t fe = hipGetLastError();  // never run the solve on stale counters
+    if (fe != hipSuccess) return fe;
     TriView l = L;
     RhsView b = B;
     int64_t nn = n, nr = nrhs, spin = (int64_t)1 << 22;
