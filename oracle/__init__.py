@@ -19,6 +19,12 @@ it with ctypes and adds the error metrics computed from a residual:
 The problem itself is the one the paper sets up in Sec. IV (L x = b with
 dense lower-triangular L, extended to many right-hand sides), generalised to
 BLAS xTRSM flags.
+
+The Cholesky factorisation (the application the paper names next, Sec. VIII)
+lives in ``chol_oracle.c``: ``potrf`` is its definition written out column by
+column, and ``chol_backward_error`` the componentwise backward error
+``max |A - F F^T|_ij / (|F||F|^T)_ij`` over entries of the stored triangle
+(Higham Thm 10.3 bounds it by gamma_{n+1}), with the residual by Dot2.
 """
 from __future__ import annotations
 
@@ -55,6 +61,11 @@ def _lib() -> ctypes.CDLL:
                                              ptr, i64, ptr, i64, ptr, i64, cint]
         lib.oracle_opnorm.restype = dbl
         lib.oracle_opnorm.argtypes = [cint, cint, cint, i64, ptr, i64, cint]
+        lib.oracle_potrf.restype = cint
+        lib.oracle_potrf.argtypes = [cint, i64, ptr, i64]
+        lib.oracle_chol_residual.restype = None
+        lib.oracle_chol_residual.argtypes = [cint, i64, ptr, i64, ptr, i64, i64, ptr, ptr, ptr,
+                                             ptr]
         _LIB = lib
     return _LIB
 
@@ -209,3 +220,53 @@ def forward_error(X: np.ndarray, Xref: np.ndarray, side: int = LEFT) -> float:
     with np.errstate(invalid="ignore", divide="ignore"):
         e = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
     return float(np.max(e, initial=0.0))
+
+
+def potrf(uplo: int, A: np.ndarray):
+    """Cholesky factor of the symmetric positive definite A (lower: A = L L^T,
+    upper: A = U^T U), in a copy of A; returns (F, info) with info 0 or the
+    order of the first leading minor found not positive definite.  Only the
+    uplo triangle of A is read; the other strict triangle of F is A's."""
+    F = _f64_fortran(A).copy(order="F")
+    n = F.shape[0]
+    if F.shape[1] != n:
+        raise ValueError("A must be square")
+    info = _lib().oracle_potrf(uplo, n, F.ctypes.data, max(1, n))
+    return F, int(info)
+
+
+def chol_residual(uplo: int, A: np.ndarray, F: np.ndarray, pairs: np.ndarray):
+    """(r, d) at the entries (i, j), i >= j, of the factor's lower storage
+    (for uplo 1 the entry (j, i) of U): r = A - F F^T by Dot2, d = |F||F|^T."""
+    A = _f64_fortran(A)
+    F = _f64_fortran(F)
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    if np.any(pairs[:, 0] < pairs[:, 1]):
+        raise ValueError("pairs must have i >= j")
+    pi = np.ascontiguousarray(pairs[:, 0])
+    pj = np.ascontiguousarray(pairs[:, 1])
+    r = np.zeros(len(pairs))
+    d = np.zeros(len(pairs))
+    _lib().oracle_chol_residual(uplo, A.shape[0], A.ctypes.data, max(1, A.shape[0]),
+                                F.ctypes.data, max(1, F.shape[0]), len(pairs), pi.ctypes.data,
+                                pj.ctypes.data, r.ctypes.data, d.ctypes.data)
+    return r, d
+
+
+def lower_pairs(n: int) -> np.ndarray:
+    """Every (i, j) with n > i >= j >= 0."""
+    i, j = np.tril_indices(n)
+    return np.stack([i, j], axis=1)
+
+
+def chol_backward_error(uplo: int, A: np.ndarray, F: np.ndarray, pairs=None) -> float:
+    """max |A - F F^T|_ij / (|F||F|^T)_ij over the given entries of the stored
+    triangle (all of them when pairs is None); an entry with a zero
+    denominator counts 0 if its residual is 0, else infinity."""
+    if pairs is None:
+        pairs = lower_pairs(np.asarray(A).shape[0])
+    r, d = chol_residual(uplo, A, F, pairs)
+    num = np.abs(r)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        w = np.where(d > 0, num / np.where(d > 0, d, 1.0), np.where(num > 0, np.inf, 0.0))
+    return float(np.max(w, initial=0.0))

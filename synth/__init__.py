@@ -25,6 +25,12 @@ workload recipe is this project's own:
   exactly in int64, so every partial sum of a substitution is an integer
   far below 2**24 and any correct solver returns X_true exactly.
 * ``batch_shapes``: log-uniform orders and right-hand-side counts.
+* ``spd_dominant`` (Cholesky inputs): symmetric, off-diagonal U(-1, 1),
+  diagonal ``1 + sum_{j != i} |A_ij|`` (strictly diagonally dominant with a
+  positive diagonal, so positive definite and well conditioned).
+* ``integer_spd``: ``A = L0 L0^T`` formed in int64 from a small-integer lower
+  L0 with diagonal in {1, 2}, so every partial sum of a Cholesky
+  factorisation is an integer and any correct one returns L0 exactly.
 """
 from __future__ import annotations
 
@@ -120,6 +126,25 @@ def integer_exact(m: int, nrhs: int, key: Key, side: int = 0, uplo: int = 0, tra
         A[np.diag_indices(k)] = np.nan
     return np.asfortranarray(A), np.asfortranarray(B.astype(np.float64)), \
         np.asfortranarray(X.astype(np.float64))
+
+
+def spd_dominant(n: int, key: Key) -> np.ndarray:
+    """Symmetric positive definite n x n: off-diagonal U(-1, 1) mirrored,
+    diagonal 1 + sum of the row's off-diagonal magnitudes."""
+    S = _strict_lower_uniform(n, key)
+    A = S + S.T
+    A[np.diag_indices(n)] = 1.0 + np.abs(A).sum(axis=1)
+    return np.asfortranarray(A)
+
+
+def integer_spd(n: int, key: Key) -> Tuple[np.ndarray, np.ndarray]:
+    """(A, L0): L0 lower with integers in [-2, 2] below the diagonal and
+    {1, 2} on it, A = L0 L0^T (full symmetric) formed exactly in int64."""
+    r = rng(key)
+    L0 = np.tril(r.integers(-2, 3, size=(n, n)).astype(np.int64), -1)
+    L0[np.diag_indices(n)] = r.choice(np.array([1, 2], dtype=np.int64), size=n)
+    A = L0 @ L0.T
+    return np.asfortranarray(A.astype(np.float64)), np.asfortranarray(L0.astype(np.float64))
 
 
 def batch_shapes(count: int, key: Key, n_range=(32, 1024), nrhs_range=(1, 256)):
