@@ -232,6 +232,29 @@ int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
                 double beta, void* C, int64_t ldc, int method, void* stream);
 
 /*
+ * Cholesky factorisation of a symmetric positive definite n x n matrix in
+ * place (LAPACK xPOTRF semantics): A = L L^T with L lower (uplo REDSEA_LOWER)
+ * or A = U^T U with U upper (REDSEA_UPPER).  Only the uplo triangle of A is
+ * read, and the factor overwrites it; the other strict triangle is neither
+ * read nor written.  The paper names this factorisation as the next
+ * application of its solver (Sec. VIII); here it is built on that solver.
+ * The matrix is split as the recursive model splits a solve (Sec. V-A):
+ * factor A11 (order n1, half of n rounded up to a multiple of nb), solve
+ * L21 L11^T = A21 with redsea_trsm, update A22 -= L21 L21^T on the matrix
+ * cores (only the tiles of the stored triangle), factor A22; blocks of order
+ * nb or less are factored by one workgroup in LDS.  nb: 0 (AUTO, 128), 32, 64
+ * or 128.  info: DEVICE int that receives 0, or i > 0 when the leading minor
+ * of order i is not positive definite; the factorisation then stops (later
+ * diagonal blocks are skipped), the factor's first i - 1 columns are final
+ * and the rest of the triangle is unspecified.  Read info after the stream
+ * has completed the call.  Temporary memory is that of redsea_trsm (the
+ * per-stream buffer, so not under graph capture).  Argument numbers: dtype 1,
+ * uplo 2, n 3, A 4, lda 5, nb 6, info 7, stream 8.
+ */
+int redsea_potrf(int dtype, int uplo, int64_t n, void* A, int64_t lda, int nb, int* info,
+                 void* stream);
+
+/*
  * Autotuner of the batched solver's task shape (spec batching pattern:
  * tile shapes picked by the project's own tuner).  Candidates t = 1..12 are
  * {16, 32} right-hand sides per wave task (a task of 32 uses each loaded
@@ -338,7 +361,9 @@ int redsea_gemm_update(int dtype, int transa, int transx, int64_t M, int64_t N, 
  * events on its stream.  redsea_trace_end() waits for those events and
  * writes, for each kernel class k < nkinds (REDSEA_KERNEL_*), the number of
  * launches, their summed duration in milliseconds and their summed
- * algorithmic flops (product: 2*M*N*K; leaf: rows^2 * right-hand sides).
+ * algorithmic flops (product: 2*M*N*K; leaf: rows^2 * right-hand sides;
+ * Cholesky block of order b: b^3 / 3; triangular update: n^2 k for an n x n
+ * triangle and k columns).
  * The three output arrays are HOST arrays of nkinds entries owned by the
  * caller.  Returns 0, -4 for bad arrays, or REDSEA_ERR_HIP.  Tracing adds a
  * pair of event records per launch; it is meant for measurement, not for
@@ -350,7 +375,9 @@ enum {
     REDSEA_KERNEL_GEMM = 2,       /* one product update (grey rectangle) */
     REDSEA_KERNEL_GEMM_GROUP = 3, /* one blocked round of products       */
     REDSEA_KERNEL_THIN = 4,       /* whole solve as one dataflow launch  */
-    REDSEA_KERNEL_CLASSES = 5
+    REDSEA_KERNEL_CHOL_LEAF = 5,  /* Cholesky of one diagonal block      */
+    REDSEA_KERNEL_SYRK = 6,       /* Cholesky trailing update, one triangle */
+    REDSEA_KERNEL_CLASSES = 7
 };
 void redsea_trace_begin(void);
 int redsea_trace_end(int64_t* launches, double* ms, double* flops, int nkinds);

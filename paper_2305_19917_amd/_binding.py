@@ -41,8 +41,9 @@ EXPORTS = (
     "redsea_pick",
     "redsea_mlp_load",
     "redsea_mfma_peak",
+    "redsea_potrf",
 )
-KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group", "thin")
+KERNEL_CLASSES = ("pack", "leaf", "gemm", "gemm_group", "thin", "chol_leaf", "syrk")
 
 SIDE = {"L": 0, "R": 1, 0: 0, 1: 1}
 UPLO = {"L": 0, "U": 1, 0: 0, 1: 1}
@@ -97,6 +98,8 @@ def lib() -> ctypes.CDLL:
     L.redsea_trmm.restype = cint
     L.redsea_trmm.argtypes = [cint, cint, cint, cint, cint, i64, i64, dbl, ptr, i64, ptr, i64, dbl,
                               ptr, i64, cint, ptr]
+    L.redsea_potrf.restype = cint
+    L.redsea_potrf.argtypes = [cint, cint, i64, ptr, i64, cint, ptr, ptr]
     L.redsea_trsm_mixed_workspace_bytes.restype = sz
     L.redsea_trsm_mixed_workspace_bytes.argtypes = [cint, i64, i64, cint]
     L.redsea_status_string.restype = ctypes.c_char_p
@@ -326,6 +329,24 @@ def trmm(A, B, C, side="L", uplo="L", trans="N", diag="N", alpha: float = 1.0,
                            C.data_ptr(), _ld(C), TRMM_METHOD[method], _stream(stream))
     _check(rc)
     return C
+
+
+def potrf(A, uplo="L", nb: int = 0, info=None, stream=None):
+    """In place Cholesky factorisation of the square column-major device tensor
+    A: A = L L^T (uplo "L") or U^T U (uplo "U"), only that triangle read and
+    written.  info: a one-element device int32 tensor (allocated when None)
+    that receives 0 or the order of the first leading minor found not
+    positive definite; it is returned, to be read once the stream is done."""
+    import torch
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    rc = lib().redsea_potrf(_dtype_code(A), UPLO[uplo], n, A.data_ptr(), _ld(A), int(nb),
+                            info.data_ptr(), _stream(stream))
+    _check(rc)
+    return info
 
 
 def gemm_update(A, X, C, transa=False, transx=False, tile: int = -1, stream=None):

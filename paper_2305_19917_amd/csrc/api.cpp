@@ -235,23 +235,6 @@ void trace_push(int kind, double flops, hipEvent_t e0, hipEvent_t e1) {
     g_tr.push_back({kind, flops, e0, e1});
 }
 
-// Runs `launch` and, when tracing, records events around it.
-template <typename F>
-hipError_t traced(int kind, double flops, hipStream_t s, F&& launch) {
-    if (!g_tr_on) return launch();
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hipErrorOutOfMemory;
-    }
-    (void)hipEventRecord(e0, s);
-    hipError_t e = launch();
-    (void)hipEventRecord(e1, s);
-    trace_push(kind, flops, e0, e1);
-    return e;
-}
-
 // ------------------------------------------------------------------ execution
 
 namespace {

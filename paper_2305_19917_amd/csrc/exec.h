@@ -55,6 +55,27 @@ size_t packed_bytes(const Canon& c, int64_t nb);
 // takes the split schedule); ignored when packed is null.
 int execute(const Canon& c, int variant, int64_t nb, hipStream_t s, void* packed = nullptr,
             int* thin_flags = nullptr);
+// Kernel timing trace (redsea_trace_begin / redsea_trace_end).
+bool trace_on();
+void trace_push(int kind, double flops, hipEvent_t e0, hipEvent_t e1);
+
+// Runs `launch` and, when tracing, records events around it on stream s.
+template <typename F>
+hipError_t traced(int kind, double flops, hipStream_t s, F&& launch) {
+    if (!trace_on()) return launch();
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hipErrorOutOfMemory;
+    }
+    (void)hipEventRecord(e0, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(e1, s);
+    trace_push(kind, flops, e0, e1);
+    return e;
+}
+
 int check_args(int dtype, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                const void* A, int64_t lda, const void* B, int64_t ldb, bool need_a);
 int pick_nb(int requested, int64_t k);

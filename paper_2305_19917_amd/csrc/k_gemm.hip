@@ -79,9 +79,9 @@ __device__ __forceinline__ void load_stage(const GemmArgs& g, int64_t m0, int64_
         else { mm = idx / C::BK; kk = idx % C::BK; }      // row of A^T storage: BK contiguous k
         const int64_t gi = m0 + mm, gk = k0 + kk;
         T v = T(0);
-        const bool inside = TRI == 0 || (TRI == 1 ? gk <= gi : gk >= gi);
+        const bool inside = TRI == 0 || TRI == 3 || (TRI == 1 ? gk <= gi : gk >= gi);
         if (gi < g.M && gk < g.K && inside) {
-            if (TRI != 0 && UNIT && gi == gk) v = T(1);
+            if ((TRI == 1 || TRI == 2) && UNIT && gi == gk) v = T(1);
             else v = AT ? a[gk + gi * g.lda] : a[gi + gk * g.lda];
         }
         ra[p] = v;
@@ -120,6 +120,8 @@ __device__ __forceinline__ void store_stage(Smem<T, C>& sm, int buf, int tid, co
     }
 }
 
+// TRI = 3: C -= A X on the entries with i <= j only (C square); the other
+// modes as in gemm_dma_kernel below.
 template <typename T, typename C, bool AT, bool RT, int TRI = 0, bool UNIT = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t n0,
                                           Smem<T, C>& sm, T beta = T(1), T gamma = T(-1)) {
@@ -177,12 +179,29 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int64_t m0, int64_t
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = m0 + wm * SM + i * 16 + Mfma<T>::row(lane, r);
                 const int64_t gj = n0 + wn * SN + j * 16 + (lane & 15);
-                if (gi < g.M && gj < g.N) {
+                if (gi < g.M && gj < g.N && (TRI != 3 || gi <= gj)) {
                     T* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    if (TRI == 0) *p = *p - acc[i][j][r];
+                    if (TRI == 0 || TRI == 3) *p = *p - acc[i][j][r];
                     else *p = (beta == T(0) ? T(0) : beta * *p) + gamma * acc[i][j][r];
                 }
             }
+}
+
+// Tile (tm, tn) of launch index b over the tiles with tm <= tn, column by
+// column: b = tn (tn + 1) / 2 + tm.  As in tile_coords, the launch index is
+// first remapped so that each of the eight XCDs (launch indices are dealt to
+// them round-robin) takes one contiguous run of b: a few consecutive tile
+// columns, whose tiles share row and column panels in that XCD's L2.
+__device__ __forceinline__ void upper_tile_coords(int64_t& tm, int64_t& tn) {
+    constexpr int64_t kXcd = 8;
+    const int64_t nwg = (int64_t)gridDim.x;
+    int64_t b = blockIdx.x;
+    if (nwg % kXcd == 0) b = (b % kXcd) * (nwg / kXcd) + b / kXcd;
+    int64_t t = (int64_t)((__builtin_sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while (t > 0 && t * (t + 1) / 2 > b) --t;
+    while ((t + 1) * (t + 2) / 2 <= b) ++t;
+    tn = t;
+    tm = b - t * (t + 1) / 2;
 }
 
 template <typename T, typename C, bool AT, bool RT>
@@ -465,7 +484,10 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
     }
 }
 
-// TRI = 0: C -= A X.  TRI = 1 / 2: A is the lower / upper triangle of its
+// TRI = 0: C -= A X.  TRI = 3: the same on the entries with i <= j only (C
+// square, equal square tiles; the grid covers the tiles that meet that
+// triangle): with X = A^T stored as A, the symmetric update of one triangle of
+// a Cholesky factorisation's trailing matrix.  TRI = 1 / 2: A is the lower / upper triangle of its
 // storage (the other triangle is never used, whatever it holds; with UNIT the
 // diagonal is taken as 1) and C := beta C + gamma A X (C not read when beta
 // is 0): the triangular product, and with gamma = -1 the residual of a
@@ -480,10 +502,14 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
                                                                       double gamma) {
     typedef DmaCfg<BM, BN, WM, WN, MINB, AT, RT> D;
     __shared__ __attribute__((aligned(1024))) char smem[2 * D::STAGE];
+    static_assert(TRI != 3 || BM == BN, "square tiles for the triangular update");
+    constexpr bool TRIA = TRI == 1 || TRI == 2;  // triangular A operand
     const int64_t tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
     int64_t tm, tn;
     if (TRI == 0) {
         tile_coords(tiles_m, tiles_n, tm, tn);
+    } else if (TRI == 3) {
+        upper_tile_coords(tm, tn);
     } else {
         // Triangle: a row tile's work grows with its distance into the
         // triangle.  Rows are taken heaviest first, and consecutive
@@ -535,7 +561,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
         const double* sx = (const double*)(st + D::OA::BYTES);
         const int64_t k0 = kt * kDmaBk;
         // a stage crossing the diagonal of this row tile (uniform)
-        const bool diag = TRI != 0 && k0 + kDmaBk > m0 && k0 < m0 + BM;
+        const bool diag = TRIA && k0 + kDmaBk > m0 && k0 < m0 + BM;
         if (kt + 1 < ke)
             dma_stage<D, AT, RT, DW>(g, m0, n0, (kt + 1) * kDmaBk, smem + ((kt + 1) & 1) * D::STAGE,
                                      wave, lane);
@@ -551,7 +577,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
             double fa[D::FM], fx[D::FN];
 #pragma unroll
             for (int i = 0; i < D::FM; ++i) fa[i] = sa[oa[ks] + i * D::OA::fstride()];
-            if (TRI != 0 && diag) {
+            if (TRIA && diag) {
 #pragma unroll
                 for (int i = 0; i < D::FM; ++i) fa[i] = mask(fa[i], i, k0 + 4 * ks + (lane >> 4));
             }
@@ -565,7 +591,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
         }
 #pragma unroll
         for (int i = 0; i < D::FM; ++i) la[i] = sa[oa[3] + i * D::OA::fstride()];
-        if (TRI != 0 && diag) {
+        if (TRIA && diag) {
 #pragma unroll
             for (int i = 0; i < D::FM; ++i) la[i] = mask(la[i], i, k0 + 12 + (lane >> 4));
         }
@@ -591,9 +617,9 @@ __global__ __launch_bounds__(64 * WM * WN, MINB) void gemm_dma_kernel(GemmArgs g
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = m0 + wm * D::SM + i * 16 + (lane >> 4) + 4 * r;
                 const int64_t gj = n0 + wn * D::SN + j * 16 + (lane & 15);
-                if (gi < g.M && gj < g.N) {
+                if (gi < g.M && gj < g.N && (TRI != 3 || gi <= gj)) {
                     double* p = RT ? c + gj + gi * g.ldc : c + gi + gj * g.ldc;
-                    if (TRI == 0) *p = *p - acc[i][j][r];
+                    if (TRI == 0 || TRI == 3) *p = *p - acc[i][j][r];
                     else *p = (beta == 0.0 ? 0.0 : beta * *p) + gamma * acc[i][j][r];
                 }
             }
@@ -647,6 +673,15 @@ hipError_t residual_launch(const GemmArgs& g, double beta, double gamma, hipStre
     hipLaunchKernelGGL((residual_kernel<T, C, AT, RT, TRI, UNIT>), dim3((unsigned)tiles),
                        dim3(C::NT), 0, s, g, (T)beta, (T)gamma);
     return hipGetLastError();
+}
+
+template <typename T, typename C, bool AT, bool RT>
+__global__ __launch_bounds__(C::NT, C::MINB) void syrk_kernel(GemmArgs g) {
+    static_assert(C::BM == C::BN, "square tiles");
+    __shared__ Smem<T, C> sm;
+    int64_t tm, tn;
+    upper_tile_coords(tm, tn);
+    gemm_tile<T, C, AT, RT, 3>(g, tm * C::BM, tn * C::BN, sm);
 }
 
 template <typename T, typename C, bool AT, bool RT>
@@ -782,7 +817,47 @@ hipError_t residual_t(bool at, bool rt, bool unit, const GemmArgs& g, double bet
     return residual_u<T, true, true, TRI>(unit, g, beta, gamma, s);
 }
 
+// Triangular update on square tiles of B: FP64 direct-to-LDS where the shape
+// allows it, else the register-staged tile of the same size.
+template <typename T, int B, int WM, int WN, int MINB, typename Fallback, bool AT, bool RT>
+hipError_t syrk_tiles(const GemmArgs& g, hipStream_t s) {
+    const int64_t t = (g.M + B - 1) / B, tiles = t * (t + 1) / 2;
+    if constexpr (sizeof(T) == 8) {
+        if (dma_ok<B, B, AT, RT>(g)) {
+            hipLaunchKernelGGL((gemm_dma_kernel<B, B, WM, WN, MINB, AT, RT, 3>),
+                               dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, 1.0, -1.0);
+            return hipGetLastError();
+        }
+        if (dma_span_ok<B, B, AT, RT>(g)) {
+            hipLaunchKernelGGL((gemm_dma_kernel<B, B, WM, WN, MINB, AT, RT, 3, false, true>),
+                               dim3((unsigned)tiles), dim3(64 * WM * WN), 0, s, g, 1.0, -1.0);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((syrk_kernel<T, Fallback, AT, RT>), dim3((unsigned)tiles),
+                       dim3(Fallback::NT), 0, s, g);
+    return hipGetLastError();
+}
+
+// 128 x 128 tiles on eight waves once the triangle has enough of them to fill
+// the GPU (order 4096: 528 tiles), 64 x 64 tiles below (order 2048: 528
+// instead of 136).
+template <typename T, bool AT, bool RT>
+hipError_t syrk_t(const GemmArgs& g, hipStream_t s) {
+    if (g.M >= 4096) return syrk_tiles<T, 128, 4, 2, 2, Tile1, AT, RT>(g, s);
+    return syrk_tiles<T, 64, 2, 2, 4, Tile3, AT, RT>(g, s);
+}
+
 }  // namespace
+
+hipError_t launch_syrk(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s) {
+    if (g.M != g.N) return hipErrorInvalidValue;
+    if (g.M <= 0 || g.K <= 0) return hipSuccess;
+    if (a_trans == rhs_trans) return hipErrorInvalidValue;
+    if (dtype == 0)
+        return a_trans ? syrk_t<double, true, false>(g, s) : syrk_t<double, false, true>(g, s);
+    return a_trans ? syrk_t<float, true, false>(g, s) : syrk_t<float, false, true>(g, s);
+}
 
 hipError_t launch_trmm(int dtype, bool a_trans, bool rhs_trans, int tri, bool unit, double beta,
                        double gamma, const GemmArgs& g, hipStream_t s) {

@@ -64,6 +64,14 @@ struct GemmArgs {
 // With gamma = -1 this is the residual R = beta B - M X of a solve.
 hipError_t launch_trmm(int dtype, bool a_trans, bool rhs_trans, int tri, bool unit, double beta,
                        double gamma, const GemmArgs& g, hipStream_t s);
+// Product update restricted to one triangle: C(i, j) -= sum_k A(i, k) X(k, j)
+// for i <= j only (M == N; the entries with i > j are neither read nor
+// written), layouts as in a product update, with a_trans != rhs_trans: the
+// two layouts in which X = A^T stored as A (x = a, ldx = lda) makes this the
+// trailing update A22 -= L21 L21^T of a lower Cholesky factorisation (a_trans
+// false: C's i <= j is the storage's lower triangle) or A22 -= U12^T U12 of an
+// upper one (a_trans true).  Any other operands are allowed too.
+hipError_t launch_syrk(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s);
 // tile < 0 picks the default tile configuration for the shape.
 hipError_t launch_gemm(int dtype, bool a_trans, bool rhs_trans, const GemmArgs& g, hipStream_t s,
                        int tile = -1);
@@ -98,6 +106,19 @@ hipError_t launch_diag_extremes(int dtype, const TriView& T, int64_t k, double* 
 int64_t thin_flag_count(int64_t n, int64_t nrhs);
 hipError_t launch_thin(int dtype, const TriView& L, const RhsView& B, int64_t n, int64_t ncols,
                        bool unit, int* flags, hipStream_t s);
+
+// Cholesky factorisation of one diagonal block of order b <= kCholLeafMax in
+// place: the lower factor L of the block whose entry (i, j), i >= j, is at
+// a[i*sr + j*sc] (sr = 1, sc = lda for a lower factorisation; sr = lda, sc = 1
+// reads an upper one's U = L^T).  Only that triangle is read or written.
+// info: device int; a block does nothing when *info != 0 on entry, and sets
+// *info = col0 + j + 1 when the pivot of its column j is not positive.
+constexpr int kCholLeafMax = 128;
+constexpr int kCholLeafDefault = 128;  // leaf order when the caller leaves nb at 0
+hipError_t launch_potrf_leaf(int dtype, void* a, int64_t sr, int64_t sc, int b, int64_t col0,
+                             int* info, hipStream_t s);
+// info[0] := 0 (a kernel, not a memset, so it may sit in captured work).
+hipError_t launch_info_clear(int* info, hipStream_t s);
 
 // info[0] := 0 if every entry of the m x n matrix is finite, else `code`.
 hipError_t launch_check_finite(int dtype, const void* b, int64_t m, int64_t n, int64_t ldb,

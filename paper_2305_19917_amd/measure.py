@@ -20,6 +20,11 @@ Rows:
   batched  2000 systems, n log-uniform in [32, 1024], nrhs in [1, 256], FP64
            and FP32: every task shape, the autotuner's pick, and one plan
            launch with that pick (eager and hipGraph replay)
+  potrf    Cholesky factorisation (redsea_potrf), FP64 lower, n in {2048,
+           4096, 8192, 16384} x leaf order {32, 64, 128}, then FP64 upper and
+           FP32 lower at n = 8192: milliseconds, n^3/3 TFLOP/s and the time
+           per kernel class from the library trace
+  potrf8192  FP64 lower n = 8192 with the default leaf only (for profiling)
 
 Timing: hipEvents on the stream, B restored by a device copy outside the
 events, median of the repetitions.  Inputs are the seeded synthetic systems of
@@ -311,12 +316,42 @@ def row_batchedfp64(tile=1, runs=5):
     plan.close()
 
 
+def row_potrf(ns=(2048, 4096, 8192, 16384), nbs=(32, 64, 128), reps=3, extra=True):
+    import torch
+    import paper_2305_19917_amd as rs
+    import synth
+    cases = [(n, nb, "L", torch.float64) for n in ns for nb in nbs]
+    if extra:
+        cases += [(8192, 0, "U", torch.float64), (8192, 0, "L", torch.float32)]
+    made = {}
+    for n, nb, uplo, dt in cases:
+        if (n, dt) not in made:
+            made.clear()
+            torch.cuda.empty_cache()
+            A0 = rs.fortran_tensor(synth.spd_dominant(n, (140, n, 0))).to(dt)
+            made[(n, dt)] = (A0, A0.clone())
+        A0, A = made[(n, dt)]
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ms = _time(lambda: rs.potrf(A, uplo=uplo, nb=nb, info=info), lambda: A.copy_(A0), reps)
+        A.copy_(A0)
+        rs.trace_begin()
+        rs.potrf(A, uplo=uplo, nb=nb, info=info)
+        torch.cuda.synchronize()
+        tr = rs.trace_end()
+        _emit({"row": "potrf", "n": n, "nb": nb or "default", "uplo": uplo,
+               "dtype": "f64" if dt == torch.float64 else "f32", "ms": round(ms, 4),
+               "tflops": round(n ** 3 / 3.0 / (ms * 1e9), 3), "info": int(info.item()),
+               "kernel_ms": {k: round(v[1], 4) for k, v in tr.items() if v[0]},
+               "launches": {k: v[0] for k, v in tr.items() if v[0]}})
+
+
 ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "thincross": row_thincross,
         "widecross": row_widecross,
         "sides": row_sides,
         "mixed": row_mixed,
         "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched,
-        "batchedfp64": row_batchedfp64}
+        "batchedfp64": row_batchedfp64, "potrf": row_potrf,
+        "potrf8192": lambda: row_potrf((8192,), (0,), reps=3, extra=False)}
 
 
 def main(argv):

@@ -88,6 +88,16 @@ def test_batched_argument_errors():
                                  None) == -11
 
 
+@pytest.mark.parametrize("args,code", [
+    ((7, 0, 4, 8, 4, 0, 8), -1), ((0, 2, 4, 8, 4, 0, 8), -2), ((0, 0, -1, 8, 4, 0, 8), -3),
+    ((0, 0, 4, 8, 3, 0, 8), -5), ((0, 0, 4, 8, 4, 48, 8), -6), ((0, 0, 4, 8, 4, 256, 8), -6),
+    ((0, 0, 4, 8, 4, 0, None), -7), ((0, 0, 4, None, 4, 0, 8), -4),
+])
+def test_potrf_argument_errors(args, code):
+    # checked before any device work, so no GPU is needed
+    assert rs.lib().redsea_potrf(*args, None) == code
+
+
 def test_schedule_argument_errors():
     L = rs.lib()
     assert L.redsea_schedule(5, 10, 16, None, 0) == -1
