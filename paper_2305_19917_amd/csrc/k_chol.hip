@@ -8,10 +8,11 @@
 // grid holds the block 2-D cyclically in registers: thread (tr, tk) owns the
 // entries (tr + 32 p, tk + 32 q), (B/32)^2 of them.  Step j (right-looking):
 // the owners of column j publish it to LDS (double-buffered, so one barrier
-// per step), every thread reads the pivot d_j = A(j, j) and updates its own
-// entries of the trailing triangle, A(r, k) -= A(r, j) (A(k, j) / d_j),
-// which is l_rj l_kj with l = a / sqrt(d); the update touches registers
-// only, so its LDS reads pipeline.  At the end every entry is divided by the
+// per step) and the pivot's owner publishes 1 / d_j beside it; every thread
+// reads the pivot d_j = A(j, j) and updates its own entries of the trailing
+// triangle, A(r, k) -= A(r, j) (A(k, j) / d_j), which is l_rj l_kj with
+// l = a / sqrt(d); the update touches registers only, so its LDS reads
+// issue together.  At the end every entry is divided by the
 // square root of its column's pivot (the diagonal becomes that root): the
 // same correctly rounded l_rk = a_rk / l_kk as column-by-column scaling.  A
 // pivot that is not positive (or NaN) stops the block: info := its global
@@ -28,11 +29,11 @@ namespace redsea {
 
 namespace {
 
-// G x G threads; each holds (B/G) x (B/G) entries of the block.  A step's
-// time is the serial instruction stream of one wave (its share of the update,
-// the reads of the published column and the pivot's reciprocal), so more,
-// smaller shares win: at B = 128 the 32 x 32 grid (16 entries per thread)
-// took 85 us per block, a 16 x 16 grid (64 entries) 142 us.
+// G x G threads; each holds (B/G) x (B/G) entries of the block.  At B = 128
+// the 32 x 32 grid (16 entries per thread) takes 86 us per block, a 16 x 16
+// grid (64 entries per thread, four waves) took 142 us: a step is a chain of
+// barrier, LDS round trips and one wave's share of the update, and smaller
+// shares shorten it.
 constexpr int kCholGrid = 32;
 
 template <typename T, int B>
@@ -42,11 +43,15 @@ __global__ __launch_bounds__(kCholGrid * kCholGrid) void potrf_leaf_kernel(T* a,
                                                                            int* info) {
     constexpr int G = kCholGrid, NR = B / G;  // entries per thread: NR x NR
     __shared__ T col[2][B];  // column j of step j before scaling, double-buffered
+    __shared__ T rcp[2];     // 1 / A(j, j), from the pivot's owner
     if (*info != 0) return;  // uniform
     const int tid = threadIdx.x;
     const bool rowfast = sr == 1;
     const int tr = rowfast ? tid % G : tid / G;  // rows tr + G p
     const int tk = rowfast ? tid / G : tid % G;  // columns tk + G q
+    // rows that are never published (past b) read as zero, so every entry
+    // the update touches stays finite
+    for (int i = tid; i < 2 * B; i += G * G) col[i / B][i % B] = T(0);
     T v[NR][NR];  // v[p][q] = A(tr + G p, tk + G q), lower triangle (p >= q)
 #pragma unroll
     for (int p = 0; p < NR; ++p)
@@ -58,6 +63,7 @@ __global__ __launch_bounds__(kCholGrid * kCholGrid) void potrf_leaf_kernel(T* a,
     T dk[NR];  // pivots of the owned columns
 #pragma unroll
     for (int q = 0; q < NR; ++q) dk[q] = T(0);
+    __syncthreads();
     int fail = -1;
     for (int j = 0; j < b; ++j) {
         const int par = j & 1, qj = j / G;
@@ -71,6 +77,7 @@ __global__ __launch_bounds__(kCholGrid * kCholGrid) void potrf_leaf_kernel(T* a,
                     const int r = tr + G * p;
                     if (r >= j && r < b) col[par][r] = v[p][q];
                 }
+                if (tr == j % G) rcp[par] = T(1) / v[q][q];  // the pivot's owner
             }
         }
         __syncthreads();
@@ -84,24 +91,25 @@ __global__ __launch_bounds__(kCholGrid * kCholGrid) void potrf_leaf_kernel(T* a,
             for (int q = 0; q < NR; ++q)
                 if (q == qj) dk[q] = d;
         }
-        const T rd = T(1) / d;
-        // Schur complement: A(r, k) -= A(r, j) A(k, j) / d for j < k <= r;
-        // sets of G rows or columns that lie wholly at or before j are done
+        const T rd = rcp[par];
+        // Schur complement: A(r, k) -= A(r, j) (A(k, j) / d) for j < k <= r.
+        // The multiplier of a finished column (k <= j) is zero, which leaves
+        // its entries as they are; entries outside the triangle (k > r, or
+        // r >= b) are updated too and never stored.  Sets of G columns that
+        // lie wholly at or before j are skipped.
         T cr[NR], ck[NR];
 #pragma unroll
-        for (int p = 0; p < NR; ++p)
-            if (G * p + G - 1 > j) cr[p] = col[par][tr + G * p];
+        for (int p = 0; p < NR; ++p) cr[p] = col[par][tr + G * p];
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-            if (G * q + G - 1 > j) ck[q] = col[par][tk + G * q] * rd;
+        for (int q = 0; q < NR; ++q) {
+            const T c = col[par][tk + G * q];
+            ck[q] = tk + G * q > j ? c * rd : T(0);
+        }
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             if (G * q + G - 1 <= j) continue;  // uniform
 #pragma unroll
-            for (int p = q; p < NR; ++p) {
-                const int r = tr + G * p, k = tk + G * q;
-                if (k > j && k <= r && r < b) v[p][q] = v[p][q] - cr[p] * ck[q];
-            }
+            for (int p = q; p < NR; ++p) v[p][q] = v[p][q] - cr[p] * ck[q];
         }
     }
     if (fail >= 0 && tid == 0) *info = (int)(col0 + fail + 1);
