@@ -248,8 +248,10 @@ int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
  * diagonal blocks are skipped), the factor's first i - 1 columns are final
  * and the rest of the triangle is unspecified.  Read info after the stream
  * has completed the call.  Temporary memory is that of redsea_trsm (the
- * per-stream buffer, so not under graph capture).  Argument numbers: dtype 1,
- * uplo 2, n 3, A 4, lda 5, nb 6, info 7, stream 8.
+ * per-stream buffer): on a stream being captured into a graph, an order
+ * above nb returns REDSEA_ERR_UNSUPPORTED before anything is enqueued.
+ * Argument numbers: dtype 1, uplo 2, n 3, A 4, lda 5, nb 6, info 7,
+ * stream 8.
  */
 int redsea_potrf(int dtype, int uplo, int64_t n, void* A, int64_t lda, int nb, int* info,
                  void* stream);

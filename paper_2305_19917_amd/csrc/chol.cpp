@@ -92,9 +92,15 @@ extern "C" int redsea_potrf(int dtype, int uplo, int64_t n, void* A, int64_t lda
     if (!info) return -7;
     if (n > 0 && !A) return -4;
     hipStream_t s = (hipStream_t)stream;
+    const int leaf = nb ? nb : kCholLeafDefault;
+    // the panel solves take the per-stream buffer, which a graph must not
+    // capture: refuse before anything is enqueued
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) return REDSEA_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone && n > leaf) return REDSEA_ERR_UNSUPPORTED;
     if (launch_info_clear(info, s) != hipSuccess) return REDSEA_ERR_HIP;
     if (n == 0) return REDSEA_OK;
-    CholCtx c{dtype, uplo == REDSEA_UPPER, lda, nb ? nb : kCholLeafDefault, info, s,
+    CholCtx c{dtype, uplo == REDSEA_UPPER, lda, leaf, info, s,
               dtype == REDSEA_F64 ? sizeof(double) : sizeof(float)};
     return factor(c, (char*)A, 0, n);
 }

@@ -186,3 +186,26 @@ def test_large_order_sampled():
     for jj in (n - 1, 5000, 127):
         piv = A[jj, jj] - np.dot(F[jj, :jj], F[jj, :jj])
         assert abs(F[jj, jj] - np.sqrt(piv)) <= 4 * (n + 1) * U[np.float64] * F[jj, jj]
+
+
+def test_graph_capture_is_refused_before_anything_is_enqueued():
+    """Above the leaf order the panel solves need the per-stream buffer, so a
+    stream under graph capture is refused (REDSEA_ERR_UNSUPPORTED) before any
+    launch, info included; the library keeps working afterwards."""
+    n = 300
+    A, L0 = synth.integer_spd(n, (129, 0, 0))
+    dA = rs.fortran_tensor(A)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    code = None
+    with torch.cuda.graph(g, stream=s):
+        try:
+            rs.potrf(dA, info=info, stream=s)
+        except rs.RedseaError as e:
+            code = e.code
+    torch.cuda.synchronize()
+    assert code == 5
+    F, inf = _gpu_potrf(A, 0)
+    assert inf == 0 and np.array_equal(np.tril(F), L0)
