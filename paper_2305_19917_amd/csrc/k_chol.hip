@@ -12,13 +12,12 @@
 // reads the pivot d_j = A(j, j) and updates its own entries of the trailing
 // triangle, A(r, k) -= A(r, j) (A(k, j) / d_j), which is l_rj l_kj with
 // l = a / sqrt(d); the update touches registers only, so its LDS reads
-// issue together.  At the end every entry is divided by the
-// square root of its column's pivot (the diagonal becomes that root): the
-// same correctly rounded l_rk = a_rk / l_kk as column-by-column scaling.  A
-// pivot that is not positive (or NaN) stops the block: info := its global
-// column + 1, the columns before it are finished and the rest is written
-// back as it stands.  A block whose info is already set (an earlier block
-// failed) does nothing.
+// issue together.  At the end every entry is divided by the square root of
+// its column's pivot (the diagonal becomes that root): the same correctly
+// rounded l_rk = a_rk / l_kk as column-by-column scaling.  A pivot that is
+// not positive (or NaN) stops the block: info := its global column + 1, the
+// columns before it are finished and the rest is written back as it stands.
+// A block whose info is already set (an earlier block failed) does nothing.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -137,15 +136,16 @@ template <typename T>
 hipError_t leaf_t(void* a, int64_t sr, int64_t sc, int b, int64_t col0, int* info,
                   hipStream_t s) {
     T* p = (T*)a;
+    const dim3 block(kCholGrid * kCholGrid);
     if (b <= 32)
-        hipLaunchKernelGGL((potrf_leaf_kernel<T, 32>), dim3(1), dim3(kCholGrid * kCholGrid), 0, s, p, sr, sc,
-                           b, col0, info);
+        hipLaunchKernelGGL((potrf_leaf_kernel<T, 32>), dim3(1), block, 0, s, p, sr, sc, b, col0,
+                           info);
     else if (b <= 64)
-        hipLaunchKernelGGL((potrf_leaf_kernel<T, 64>), dim3(1), dim3(kCholGrid * kCholGrid), 0, s, p, sr, sc,
-                           b, col0, info);
+        hipLaunchKernelGGL((potrf_leaf_kernel<T, 64>), dim3(1), block, 0, s, p, sr, sc, b, col0,
+                           info);
     else
-        hipLaunchKernelGGL((potrf_leaf_kernel<T, 128>), dim3(1), dim3(kCholGrid * kCholGrid), 0, s, p, sr,
-                           sc, b, col0, info);
+        hipLaunchKernelGGL((potrf_leaf_kernel<T, 128>), dim3(1), block, 0, s, p, sr, sc, b, col0,
+                           info);
     return hipGetLastError();
 }
 

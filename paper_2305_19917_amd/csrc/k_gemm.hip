@@ -486,8 +486,9 @@ __device__ __forceinline__ void dma_stage(const GemmArgs& g, int64_t m0, int64_t
 
 // TRI = 0: C -= A X.  TRI = 3: the same on the entries with i <= j only (C
 // square, equal square tiles; the grid covers the tiles that meet that
-// triangle): with X = A^T stored as A, the symmetric update of one triangle of
-// a Cholesky factorisation's trailing matrix.  TRI = 1 / 2: A is the lower / upper triangle of its
+// triangle): with X = A^T stored as A, the symmetric update of one triangle
+// of a Cholesky factorisation's trailing matrix.  TRI = 1 / 2: A is the
+// lower / upper triangle of its
 // storage (the other triangle is never used, whatever it holds; with UNIT the
 // diagonal is taken as 1) and C := beta C + gamma A X (C not read when beta
 // is 0): the triangular product, and with gamma = -1 the residual of a
