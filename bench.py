@@ -15,6 +15,9 @@ the metric's mixed-precision leg: n = 16384, nrhs = 4096 at kappa_1 ~ 1e4,
 plain FP64 against FP32 and BF16 inner solves with FP64 refinement to a
 backward error of 1e-12 (wall time, refinement statistics, oracle-sampled
 backward error).  `value` is the FP64 throughput of the n = 8192 workload.
+A last key times the Cholesky factorisation built on the solve
+(redsea_potrf, FP64 lower, n = 8192) with the oracle's componentwise
+backward error on sampled entries.
 """
 import argparse
 import json
@@ -173,6 +176,62 @@ def mixed_leg(n, nrhs, reps, log):
     return out
 
 
+def cholesky_leg(n, reps, log):
+    """redsea_potrf, FP64 lower, n x n symmetric diagonally dominant matrix
+    (off-diagonal U(-1, 1) mirrored, diagonal 1 + row sum of magnitudes):
+    median time of `reps` factorisations after a warm-up (the matrix restored
+    by a device copy outside the events), n^3/3 TFLOP/s, info, the time per
+    kernel class of one traced factorisation, and the oracle's componentwise
+    backward error max |A - L L^T| / (|L||L^T|) on sampled entries.  Any
+    failure is reported in the record, never raised."""
+    try:
+        import numpy as np
+        import torch
+
+        import oracle
+        import paper_2305_19917_amd as rs
+        import synth
+
+        log("cholesky leg: generating n=%d" % n)
+        A = synth.spd_dominant(n, (140, n, 0))
+        dA0 = rs.fortran_tensor(A)
+        dA = dA0.clone()
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        stream = torch.cuda.current_stream()
+        times = []
+        for r in range(reps + 1):
+            dA.copy_(dA0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rs.potrf(dA, info=info, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            if r > 0:
+                times.append(e0.elapsed_time(e1))
+        times.sort()
+        ms = times[len(times) // 2]
+        dA.copy_(dA0)
+        rs.trace_begin()
+        rs.potrf(dA, info=info, stream=stream)
+        torch.cuda.synchronize()
+        tr = rs.trace_end()
+        F = np.tril(dA.cpu().numpy())
+        g = synth.rng((140, n, 1))
+        i = g.integers(0, n, size=1000)
+        j = np.minimum((g.random(1000) * (i + 1)).astype(np.int64), i)
+        pairs = np.concatenate([np.stack([i, j], axis=1), [[n - 1, n - 1], [n - 1, 0]]])
+        return {"workload": "FP64 Cholesky (redsea_potrf) lower, n=%d, leaf order 128, "
+                            "symmetric diagonally dominant" % n,
+                "reps": reps, "ms": round(ms, 3),
+                "tflops": round(n ** 3 / 3.0 / (ms * 1e-3) / 1e12, 3),
+                "info": int(info.item()),
+                "kernel_ms": {k: round(v[1], 3) for k, v in tr.items() if v[0]},
+                "omega_sampled": oracle.chol_backward_error(0, A, F, pairs)}
+    except Exception as e:  # the headline line must not depend on this leg
+        return {"error": repr(e)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -196,6 +255,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--mixed-reps", type=int, default=3)
+    ap.add_argument("--no-cholesky", action="store_true", help="skip the Cholesky leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -278,6 +338,7 @@ def main():
     eta = oracle.backward_error(0, 0, 0, 0, 1.0, L, np.asfortranarray(B[:, cols]), Xs)
 
     mixed = None if args.no_mixed else mixed_leg(16384, 4096, args.mixed_reps, log)
+    chol = None if args.no_cholesky else cholesky_leg(8192, 3, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -321,6 +382,7 @@ def main():
                      "launches_per_step": g_launch // max(1, args.steps)},
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "cholesky": chol,
     }
     print(json.dumps(out), flush=True)
 
