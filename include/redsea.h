@@ -162,7 +162,8 @@ int redsea_trsm_noalloc(int dtype, int side, int uplo, int trans, int diag, int6
 
 /*
  * Variable-size batch of independent solves sharing flags and alpha
- * (spec batching pattern; each system is the solve of Sec. IV).
+ * (thousands of uneven systems in one launch; each system is the solve of
+ * Sec. IV).
  * m, n, lda, ldb: HOST arrays of `count` entries.  A, B: HOST arrays of
  * `count` DEVICE pointers.  info: DEVICE int array of `count` entries that
  * receives 0 or REDSEA_ERR_NONFINITE for a system whose result holds a
@@ -257,8 +258,8 @@ int redsea_potrf(int dtype, int uplo, int64_t n, void* A, int64_t lda, int nb, i
                  void* stream);
 
 /*
- * Autotuner of the batched solver's task shape (spec batching pattern:
- * tile shapes picked by the project's own tuner).  Candidates t = 1..12 are
+ * Autotuner of the batched solver's task shape (the library picks the task
+ * shape with its own tuner rather than a fixed rule).  Candidates t = 1..12 are
  * {16, 32} right-hand sides per wave task (a task of 32 uses each loaded
  * block of the triangle for two groups of 16, halving reads of the matrix)
  * x {1, 2, 4} steps of the left-looking product with operands in flight
@@ -292,8 +293,9 @@ typedef struct {
 
 /*
  * FP64 solve computed with low-precision inner solves and FP64 iterative
- * refinement (spec precision pattern): X0 from an FP32 (inner = 1) or
- * BF16-product (inner = 2) solve, then repeated R = alpha B - op(A) X in FP64
+ * refinement (FP64 accuracy from faster low-precision solves): X0 from an
+ * FP32 (inner = 1) or BF16-product (inner = 2) solve, then repeated
+ * R = alpha B - op(A) X in FP64
  * (with inner | REDSEA_RESIDUAL_INT8: by the exact integer emulation of
  * redsea_trmm's REDSEA_TRMM_INT8 method, a labelled variant),
  * a low-precision correction solve and X += D in FP64, until the normwise
@@ -395,8 +397,8 @@ enum { REDSEA_CANDIDATES = 45 };
 int redsea_candidate(int index, int* variant, int* nb, int* precision);
 
 /*
- * Exhaustive autotuner for one shape (spec learned part: the timings it
- * produces train the picker, and the picker falls back to it).  Generates a
+ * Exhaustive autotuner for one shape (the timings it produces train the
+ * picker, and the picker falls back to it).  Generates a
  * left/lower/no-transpose system of order n with nrhs right-hand sides on the
  * device (strict lower part uniform in (-1, 1) from a counter-based hash of
  * (seed, i, j); diagonal 1 + sum|row| when c <= 0, else the constant

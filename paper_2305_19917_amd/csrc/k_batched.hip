@@ -1,6 +1,6 @@
 // Persistent batched solver: many independent triangular systems of uneven
 // order and right-hand-side count in one launch (the solve of Sec. IV per
-// system; spec batching pattern).
+// system).
 //
 // Work is a list of tasks (system, tile of up to 16 right-hand sides) in one
 // queue per XCD (a system's tiles in one queue, each queue longest-first).
