@@ -305,23 +305,50 @@ int lookahead_for(hipStream_t s, Lookahead* out) {
 // first rows, only those rows are updated on the stream s; the rest of the
 // product runs on the helper stream `side`, concurrently with that leaf, and
 // the next product (which writes the same rows as the rest) waits for it.
-// Every FP64 product tile runs the same MFMA sequence in the same k order, so
-// splitting a product's rows changes no result bit.
+// A blocked round (several block products) followed by a leaf is split the
+// same way: the blocks that write the leaf's rows run on s, the others on
+// `side` while the leaf runs (they read only blocks solved before and write
+// other rows).  Both parts keep the round's tile configuration, and every
+// product tile runs the same MFMA sequence in the same k order, so the split
+// changes no result bit.  Any later leaf or round waits for the helper first.
 int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, const void* packed,
               hipStream_t s, const Lookahead* la = nullptr) {
     const size_t es = c.dtype == REDSEA_F64 ? 8 : 4;
     hipStream_t side = la ? la->helper : nullptr;
     const hipEvent_t ev[2] = {la ? la->ev[0] : nullptr, la ? la->ev[1] : nullptr};
     bool pending = false;  // a product tail is in flight on `side`
+    int64_t overlap_row = -1;  // row0 of the one leaf that may run beside it
     auto join = [&]() -> bool {
         if (!pending) return true;
         pending = false;
         return hipStreamWaitEvent(s, ev[1], 0) == hipSuccess;
     };
+    // block products as grouped launches of at most kMaxGroup, one tile
+    // configuration for all of them
+    auto launch_blocks = [&](const std::vector<GemmArgs>& blocks, int tile,
+                             hipStream_t st) -> bool {
+        GemmGroup grp;
+        grp.count = 0;
+        for (size_t q = 0; q < blocks.size(); ++q) {
+            grp.g[grp.count++] = blocks[q];
+            if (grp.count == kMaxGroup || q + 1 == blocks.size()) {
+                double fl = 0.0;
+                for (int u = 0; u < grp.count; ++u) fl += 2.0 * grp.g[u].M * grp.g[u].N * grp.g[u].K;
+                if (traced(REDSEA_KERNEL_GEMM_GROUP, fl, st, [&] {
+                        return launch_gemm_group(c.dtype, c.op_trans, c.rhs_trans, grp, st, tile);
+                    }) != hipSuccess)
+                    return false;
+                grp.count = 0;
+            }
+        }
+        return true;
+    };
     size_t i = 0;
     while (i < tasks.size()) {
         const Task& t = tasks[i];
         if (t.kind == TASK_LEAF) {
+            if (pending && t.row0 != overlap_row && !join()) return REDSEA_ERR_HIP;
+            overlap_row = -1;
             const char* pb =
                 (const char*)packed + (size_t)(t.row0 / kleaf) * leaf_block_elems((int)kleaf) * es;
             const double fl = (double)t.rows * t.rows * c.nrhs;
@@ -350,12 +377,35 @@ int run_tasks(const Canon& c, const std::vector<Task>& tasks, int64_t kleaf, con
                 hipEventRecord(ev[1], side) != hipSuccess)
                 return REDSEA_ERR_HIP;
             pending = true;
+            overlap_row = tasks[j].row0;
             if (traced(REDSEA_KERNEL_GEMM, 2.0 * gh.M * gh.N * gh.K, s, [&] {
                     return launch_gemm(c.dtype, c.op_trans, c.rhs_trans, gh, s);
                 }) != hipSuccess)
                 return REDSEA_ERR_HIP;
             i = j;
             continue;
+        }
+        if (side && !c.gemm_bf16 && j - i > 1 && j < tasks.size() && tasks[j].kind == TASK_LEAF) {
+            const Task& lf = tasks[j];
+            std::vector<GemmArgs> head, tail;
+            for (size_t q = i; q < j; ++q) {
+                const Task& b = tasks[q];
+                const bool hits = b.row0 < lf.row0 + lf.rows && lf.row0 < b.row0 + b.rows;
+                (hits ? head : tail).push_back(gemm_args(c, b.row0, b.rows, b.col0, b.cols));
+            }
+            if (!tail.empty()) {
+                const GemmArgs f = gemm_args(c, t.row0, t.rows, t.col0, t.cols);
+                const int tile = gemm_default_tile(c.dtype, f.M, f.N, f.K);
+                if (hipEventRecord(ev[0], s) != hipSuccess ||
+                    hipStreamWaitEvent(side, ev[0], 0) != hipSuccess || !launch_blocks(tail, tile, side) ||
+                    hipEventRecord(ev[1], side) != hipSuccess)
+                    return REDSEA_ERR_HIP;
+                pending = true;
+                overlap_row = lf.row0;
+                if (!head.empty() && !launch_blocks(head, tile, s)) return REDSEA_ERR_HIP;
+                i = j;
+                continue;
+            }
         }
         if (c.gemm_bf16) {
             for (size_t q = i; q < j; ++q) {

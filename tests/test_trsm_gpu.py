@@ -338,13 +338,14 @@ def test_graph_capture_is_refused_not_dangling():
                                        (1000, 100, 64)])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_lookahead_changes_no_bit(k, nrhs, nb, dtype, monkeypatch):
-    """Look-ahead (the rows of a product beyond the next leaf updated on a
-    helper stream while that leaf runs) gives exactly the bits of the
-    sequential order."""
+    """Look-ahead (the rows of a product beyond the next leaf, or the blocks
+    of a blocked round that the next leaf does not read, updated on a helper
+    stream while that leaf runs) gives exactly the bits of the sequential
+    order."""
     L = synth.dominant_lower(k, (24, k, 0))
     B = synth.rhs_normal(k, nrhs, (24, k, 1))
     monkeypatch.setenv("REDSEA_THIN", "0")  # the split schedules, whatever the width
-    for variant in ("recursive", "iterative"):
+    for variant in ("recursive", "iterative", "blocked"):
         monkeypatch.setenv("REDSEA_LOOKAHEAD", "0")
         X0 = gpu_solve(L, B, variant=variant, nb=nb, dtype=dtype)
         monkeypatch.setenv("REDSEA_LOOKAHEAD", "1")
