@@ -25,6 +25,8 @@ Rows:
            FP32 lower at n = 8192: milliseconds, n^3/3 TFLOP/s and the time
            per kernel class from the library trace
   potrf8192  FP64 lower n = 8192 with the default leaf only (for profiling)
+  blockedla  FP64 n = 8192, blocked model, nb 256, nrhs in {128, 512, 1024}:
+           look-ahead off against on (REDSEA_LOOKAHEAD = 0 / 1)
 
 Timing: hipEvents on the stream, B restored by a device copy outside the
 events, median of the repetitions.  Inputs are the seeded synthetic systems of
@@ -345,13 +347,32 @@ def row_potrf(ns=(2048, 4096, 8192, 16384), nbs=(32, 64, 128), reps=3, extra=Tru
                "launches": {k: v[0] for k, v in tr.items() if v[0]}})
 
 
+def row_blockedla(n=8192, widths=(128, 512, 1024), nb=256, reps=5):
+    import paper_2305_19917_amd as rs
+    import synth
+    dL = rs.fortran_tensor(synth.dominant_lower(n, (1, 0, 0)))
+    for nrhs in widths:
+        dB0 = rs.fortran_tensor(synth.rhs_normal(n, nrhs, (1, 0, 1)))
+        dB = dB0.clone()
+        rec = {"row": "blockedla", "n": n, "nrhs": nrhs, "nb": nb}
+        for la in ("0", "1"):
+            os.environ["REDSEA_LOOKAHEAD"] = la
+            ms = _time(lambda: rs.trsm(dL, dB, variant="blocked", nb=nb), lambda: dB.copy_(dB0),
+                       reps)
+            rec["ms_lookahead_" + ("off" if la == "0" else "on")] = round(ms, 4)
+        os.environ.pop("REDSEA_LOOKAHEAD", None)
+        rec["tflops_on"] = round(float(n) * n * nrhs / (rec["ms_lookahead_on"] * 1e9), 3)
+        _emit(rec)
+
+
 ROWS = {"peak": row_peak, "small": row_small, "thin": row_thin, "thincross": row_thincross,
         "widecross": row_widecross,
         "sides": row_sides,
         "mixed": row_mixed,
         "mixed1e4": lambda: row_mixed((1e4,), reps=1), "batched": row_batched,
         "batchedfp64": row_batchedfp64, "potrf": row_potrf,
-        "potrf8192": lambda: row_potrf((8192,), (0,), reps=3, extra=False)}
+        "potrf8192": lambda: row_potrf((8192,), (0,), reps=3, extra=False),
+        "blockedla": row_blockedla}
 
 
 def main(argv):
