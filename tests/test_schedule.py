@@ -53,6 +53,37 @@ def test_dependencies(variant, m, nb):
     assert solved.all()
 
 
+@pytest.mark.parametrize("variant", ["recursive", "iterative", "blocked"])
+@pytest.mark.parametrize("m,nb", [(64, 16), (1000, 64), (2048, 128), (4096, 32), (8192, 256),
+                                  (333, 32)])
+def test_lookahead_splits_are_safe(variant, m, nb):
+    """The executor's look-ahead runs, beside the leaf that follows a
+    launch, every product of that launch that does not write the leaf's rows
+    (for a single product: the rows past the leaf).  That is only race-free
+    if such a leaf exists right after the launch, a product either writes
+    all of the leaf's rows or none of them (blocked rounds; a single product
+    starts at the leaf's first row), and nothing of the launch reads the rows
+    the leaf writes."""
+    t = _tasks(variant, m, nb)
+    for k in range(len(t) - 1):
+        kind, r0, rows, c0, cols, rnd = t[k]
+        nxt = t[k + 1]
+        if kind != GEMM or nxt[0] != LEAF:
+            continue
+        leaf_r0, leaf_rows = nxt[1], nxt[2]
+        launch = [x for x in t if x[0] == GEMM and x[5] == rnd]
+        for _, b_r0, b_rows, b_c0, b_cols, _ in launch:
+            overlap = b_r0 < leaf_r0 + leaf_rows and leaf_r0 < b_r0 + b_rows
+            if len(launch) > 1:
+                assert not overlap or (b_r0 == leaf_r0 and b_rows == leaf_rows)
+            else:
+                assert b_r0 == leaf_r0 and b_rows >= leaf_rows
+            # reads only rows solved before the leaf
+            assert b_c0 + b_cols <= leaf_r0
+    kinds = [x[0] for x in t]
+    assert not any(a == LEAF and b == LEAF for a, b in zip(kinds, kinds[1:]))
+
+
 def test_each_product_pair_applied_once():
     """Every (row, column) pair of the strict lower triangle is subtracted
     exactly once, at leaf granularity."""
