@@ -341,8 +341,12 @@ def potrf(A, uplo="L", nb: int = 0, info=None, stream=None):
     n = A.shape[0]
     if A.shape[1] != n:
         raise ValueError("A must be square")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
+    elif not info.is_cuda or info.dtype != torch.int32 or info.numel() < 1:
+        raise ValueError("info must be a device int32 tensor of at least one element")
     rc = lib().redsea_potrf(_dtype_code(A), UPLO[uplo], n, A.data_ptr(), _ld(A), int(nb),
                             info.data_ptr(), _stream(stream))
     _check(rc)

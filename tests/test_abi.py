@@ -180,3 +180,12 @@ def test_batched_tune_argument_errors():
     assert L.redsea_batched_tune(0, 0, 1, k, r, 1, None, None) == -8
     assert L.redsea_batched_tune(0, 0, 0, None, None, 1, None, ctypes.byref(best)) == 0
     assert best.value == 1
+
+
+def test_potrf_binding_refuses_host_tensors():
+    # the library writes info and the factor through device pointers: the
+    # binding refuses host tensors before any call
+    torch = pytest.importorskip("torch")
+    A = torch.zeros((4, 4), dtype=torch.float64).t()
+    with pytest.raises(ValueError):
+        rs.potrf(A)
