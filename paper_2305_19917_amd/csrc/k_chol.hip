@@ -45,9 +45,12 @@ __global__ __launch_bounds__(kCholGrid * kCholGrid) void potrf_leaf_kernel(T* a,
     __shared__ T rcp[2];     // 1 / A(j, j), from the pivot's owner
     if (*info != 0) return;  // uniform
     const int tid = threadIdx.x;
-    const bool rowfast = sr == 1;
-    const int tr = rowfast ? tid % G : tid / G;  // rows tr + G p
-    const int tk = rowfast ? tid / G : tid % G;  // columns tk + G q
+    // the owners of a column (equal tk) are one contiguous half-wave, so one
+    // wave publishes at each step, whatever the storage order (for an upper
+    // factorisation the block's loads and stores are then strided; they run
+    // once per block and mostly from L2)
+    const int tr = tid % G;  // rows tr + G p
+    const int tk = tid / G;  // columns tk + G q
     // rows that are never published (past b) read as zero, so every entry
     // the update touches stays finite
     for (int i = tid; i < 2 * B; i += G * G) col[i / B][i % B] = T(0);
