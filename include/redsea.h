@@ -243,8 +243,8 @@ int redsea_trmm(int dtype, int side, int uplo, int trans, int diag, int64_t m, i
  * factor A11 (order n1, half of n rounded up to a multiple of nb), solve
  * L21 L11^T = A21 with redsea_trsm, update A22 -= L21 L21^T on the matrix
  * cores (only the tiles of the stored triangle), factor A22; blocks of order
- * nb or less are factored by one workgroup in LDS.  nb: 0 (AUTO, 128), 32, 64
- * or 128.  info: DEVICE int that receives 0, or i > 0 when the leading minor
+ * nb or less are factored by one workgroup (the block held in registers,
+ * each column passed on through LDS).  nb: 0 (AUTO, 128), 32, 64 or 128.  info: DEVICE int that receives 0, or i > 0 when the leading minor
  * of order i is not positive definite; the factorisation then stops (later
  * diagonal blocks are skipped), the factor's first i - 1 columns are final
  * and the rest of the triangle is unspecified.  Read info after the stream

@@ -11,7 +11,7 @@
 //     A22 := A22 - L21 L21^T     (one triangle of tiles on the matrix cores),
 //     A22 = L22 L22^T            (recursively),
 // down to diagonal blocks of order nb or less, each factored by one workgroup
-// in LDS.  n1 is half the order rounded up to a multiple of nb, so every
+// (the block in registers, its columns passed on through LDS).  n1 is half the order rounded up to a multiple of nb, so every
 // leaf but the last has order nb and the big solves and products come first.
 // An upper factorisation A = U^T U runs the same steps on U = L^T through the
 // transposed storage: the solve becomes U11^T U12 = A12 (left side) and the
